@@ -1,0 +1,220 @@
+/*
+ * pmgrit.h -- C ABI of the MI355X (gfx950) MGRIT + p-multigrid solver for isogeometric
+ * discretisations of the heat equation.
+ *
+ * Method: Tielen, Moeller, Vuik, "Combining p-multigrid and multigrid reduced in time methods
+ * to obtain a scalable solver for Isogeometric Analysis" (arXiv 2107.05337).
+ *   - Problem: d_t u - kappa Lap u = f on Omega x [0,T], u(.,0) = u0, u = 0 on the boundary
+ *     (Sec. 2, eq:heat), tensor-product B-splines of degree p on n x n elements of width
+ *     h = 1/n with open uniform knot vectors (Sec. 2), implicit Euler (theta = 1), so every
+ *     time step solves (M + kappa dt K) u^{k+1} = M u^k + dt f^{k+1} (Sec. 2, eq:los; Sec. 4).
+ *   - Time parallelism: MGRIT with coarsening factor m, FCF-relaxation, injection of the
+ *     C-point residual, rediscretised coarse levels dt_l = m^l dt and ideal interpolation
+ *     (Sec. 3, eq:mgrit, eq:mgrit_coarse and the MGRIT recursion).
+ *   - Spatial solves: p-multigrid V-cycles (Sec. 4, steps 1-5) with an ILUT smoother at
+ *     degree p, direct restriction to p = 1 with the lumped-mass L2 transfers
+ *     (Sec. 4, eq:prolongation, eq:PM) and an exact solve at p = 1.
+ *
+ * Conventions for every call:
+ *   - Return value: PMGRIT_OK (0) or a negative pmgrit_status; no call aborts the process;
+ *     pmgrit_last_error() returns a thread-local message about the last failure.
+ *   - Output handles and host output arguments are left untouched on error.
+ *   - Host structs passed by pointer are copied at the call; the caller keeps ownership.
+ *   - Device pointers ("_dev") are device memory of the handle's GPU that the caller owns and
+ *     keeps alive until the work enqueued on the given stream has completed.  Streams are
+ *     hipStream_t passed as void* (NULL = the default stream).
+ *   - The handle owns every factor, schedule and workspace; all of them are allocated in
+ *     pmgrit_create, so the solve calls allocate nothing on the device.
+ *   - A handle is not thread-safe; use one handle per host thread / stream.
+ *   - Degrees of freedom: the interior tensor-product B-splines (the first and last function
+ *     per direction carry the homogeneous Dirichlet condition and are removed), numbered
+ *     lexicographically with the first parameter direction fastest: dof = iy * Nin + ix,
+ *     Nin = n + p - 2.  A time trajectory is (N_t + 1) x n_dof doubles, time-major.
+ */
+#ifndef PMGRIT_H
+#define PMGRIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PMGRIT_OK = 0,
+  PMGRIT_E_ARG = -1,            /* invalid argument or size */
+  PMGRIT_E_HIP = -2,            /* a HIP runtime call failed (message in pmgrit_last_error) */
+  PMGRIT_E_OOM = -3,            /* device or host allocation failed */
+  PMGRIT_E_FACTOR = -4,         /* ILUT produced a non-positive or non-finite pivot */
+  PMGRIT_E_SPATIAL_NOCONV = -5, /* a spatial solve hit max_vcycles before its tolerance */
+  PMGRIT_E_MGRIT_NOCONV = -6,   /* MGRIT hit max_iter before its tolerance */
+  PMGRIT_E_NONFINITE = -7,      /* NaN or Inf in a residual */
+  PMGRIT_E_STATE = -8           /* call not valid for this handle (e.g. host-only handle) */
+} pmgrit_status;
+
+/* One problem instance (Sec. 2, eq:heat; Sec. 5 benchmark setting).
+ * domain 0: unit square (F = identity).  domain 1: quarter annulus with radii 1 and 2, first
+ * parameter direction radial, second the exact rational quadratic quarter circle.
+ * Source f(x, t) = tfac(t) * sum_q amp_q m(k_q, s) m(l_q, t) in parameter coordinates (s, t)
+ * with m(0, .) = 1 and m(k, s) = sin(k pi s) for k >= 1, set by pmgrit_set_source_modes. */
+typedef struct {
+  int32_t degree_p; /* B-spline degree p >= 2 (the p = 1 level is the coarse space) */
+  int32_t n_elems;  /* n elements per direction, h = 1/n, n >= 2 */
+  int32_t domain;   /* 0 unit square, 1 quarter annulus */
+  double kappa;     /* diffusion coefficient > 0 */
+  double T;         /* end time > 0 */
+  int32_t n_steps;  /* N_t >= 1 */
+} pmgrit_problem;
+
+/* MGRIT hierarchy and stopping rule (Sec. 3; Sec. 5).  Level l has floor(N_t / m^l)
+ * intervals of size m^l dt; coarsening stops at max_levels levels or as soon as a level has
+ * at most coarsest_max intervals.  Converged when the level-0 C-point residual after
+ * FCF-relaxation, in the Euclidean norm over all C-points and dofs, is <= tol times its value
+ * in the first iteration. */
+typedef struct {
+  int32_t cfactor;      /* m >= 2 */
+  int32_t max_levels;   /* >= 2 (2 = two-level MGRIT) */
+  int32_t coarsest_max; /* stop coarsening at <= this many intervals (e.g. 8) */
+  double tol;           /* relative residual, e.g. 1e-10 */
+  int32_t max_iter;     /* MGRIT iteration cap */
+} pmgrit_mgrit_opts;
+
+/* Spatial solver (Sec. 4).  precision 0: FP64 V-cycle.  precision 1: V-cycle in FP32 as the
+ * preconditioner of FP64 iterative refinement (residual, update and the p = 1 solve in FP64).
+ * guess: initial iterate of every spatial solve -- 0 zero, 1 previous time point,
+ * 2 current value of the target point (MGRIT), 3 learned warm start (network, see
+ * pmgrit_net_load; falls back to the better of 1 and 2 by FP64 residual).
+ * trsv_block: row-block size of the blocked triangular solves (0 = autotune,
+ * 1 = plain row level-scheduling, -1 = one grid line). */
+typedef struct {
+  int32_t nu1, nu2;       /* pre-/post-smoothing steps (>= 1) */
+  double ilut_droptol;    /* ILUT drop tolerance tau (relative to the row 2-norm) */
+  int32_t ilut_fill;      /* 0: at most as many entries per row of L / U as A has there */
+  double spatial_tol;     /* stop when ||b - A x||_2 <= spatial_tol ||b||_2 */
+  int32_t max_vcycles;    /* V-cycle cap per spatial solve */
+  int32_t precision;      /* 0 FP64, 1 FP32 V-cycle inside FP64 refinement */
+  int32_t guess;          /* 0 zero, 1 previous, 2 current target, 3 learned */
+  int32_t trsv_block;     /* see above */
+} pmgrit_solver_opts;
+
+typedef struct {
+  int32_t mgrit_iters;    /* coarse corrections applied until convergence */
+  double res_hist[64];    /* relative level-0 residual after each FCF (res_hist[0] = 1) */
+  int64_t phi_calls;      /* spatial solves performed (all levels, all instances) */
+  int64_t vcycles;        /* V-cycles performed */
+  double t_setup_s;       /* wall time of pmgrit_create */
+  double t_solve_s;       /* wall time of the solve call, device-synchronised */
+} pmgrit_stats;
+
+typedef struct pmgrit_handle pmgrit_handle;
+
+/* Create a solver for n_instances problems (several instances of uneven p, h, kappa and
+ * domain are batched into the same launches).  Assembles M, K and the transfer operators on
+ * the host, factors ILUT(M + kappa dt_l K) for every time level, builds the triangular-solve
+ * schedules and the exact p = 1 solve data, and uploads everything to hip_device.
+ * hip_device = -1 builds the host-side data only (for inspection; solve calls then return
+ * PMGRIT_E_STATE).  All instances share one set of MGRIT and solver options. */
+pmgrit_status pmgrit_create(int32_t n_instances, const pmgrit_problem* probs, const pmgrit_mgrit_opts* mopts,
+                            const pmgrit_solver_opts* sopts, int32_t hip_device, pmgrit_handle** out);
+void pmgrit_destroy(pmgrit_handle* h);
+
+/* Sizes of instance inst: n_dof (degree p interior dofs), grid_n = n + p (functions per
+ * direction incl. the boundary ones), n_levels of the MGRIT hierarchy. */
+pmgrit_status pmgrit_dims(const pmgrit_handle* h, int32_t inst, int64_t* n_dof, int32_t* grid_n,
+                          int32_t* n_levels);
+
+/* Source of instance inst: n_modes separable modes (k[q], l[q], amp[q]) as described above,
+ * with time factor time_kind 0: 1, 1: exp(-t).  The load vector int f Phi_i is assembled on
+ * the host with the degree-p Gauss rule. */
+pmgrit_status pmgrit_set_source_modes(pmgrit_handle* h, int32_t inst, int32_t n_modes, const int32_t* k,
+                                      const int32_t* l, const double* amp, int32_t time_kind);
+
+/* Initial condition of instance inst as the L2 projection (consistent mass) of a sum of
+ * modes (Sec. 3: g^0 is u0 projected on the spline space).  n_modes = 0 gives u0 = 0. */
+pmgrit_status pmgrit_set_initial_modes(pmgrit_handle* h, int32_t inst, int32_t n_modes, const int32_t* k,
+                                       const int32_t* l, const double* amp);
+
+/* Initial coefficients of instance inst from a host array of n_dof doubles. */
+pmgrit_status pmgrit_set_initial_coeffs(pmgrit_handle* h, int32_t inst, const double* u0_host);
+
+/* MGRIT solve of every instance (Sec. 3).  u_out_dev[i] is instance i's trajectory buffer of
+ * (N_t + 1) x n_dof doubles on the device; on return (after the stream is synchronised by the
+ * call) it holds the converged trajectory.  stats may be NULL. */
+pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* const* u_out_dev, pmgrit_stats* stats);
+
+/* Sequential implicit Euler with the same spatial solver (block forward solve of eq:mgrit);
+ * same buffers as pmgrit_solve_mgrit. */
+pmgrit_status pmgrit_solve_sequential(pmgrit_handle* h, void* hip_stream, double* const* u_out_dev,
+                                      pmgrit_stats* stats);
+
+/* One batched spatial solve at time level `level` of instance inst (Sec. 4): for each of the
+ * nrhs right-hand sides j, solve (M + kappa dt_level K) x_j = b_j by p-multigrid V-cycles to
+ * the spatial tolerance, starting from the guess in x_j.  b_dev and x_dev are nrhs x n_dof
+ * doubles (right-hand side j contiguous), nrhs <= 4096.  vcycles_dev (nrhs int32, may be NULL)
+ * receives the V-cycle count of each solve.  Enqueued on hip_stream; the call returns after the
+ * stream has completed it. */
+pmgrit_status pmgrit_phi(pmgrit_handle* h, int32_t inst, int32_t level, int32_t nrhs, const double* b_dev,
+                         double* x_dev, int32_t* vcycles_dev, void* hip_stream);
+
+/* Host-side inspection of the assembled data of instance inst (valid for every handle).
+ * which: 0 M, 1 K, 2 A_level = M + kappa dt_level K, 3 L of ILUT(A_level) (strict lower),
+ * 4 U of ILUT(A_level) (upper incl. diagonal), 5 P_1^p (interior, n_dof x n_dof1),
+ * 6 M1, 7 K1 (degree 1 interior).  Call with rp = NULL to get shape3 = {rows, cols, nnz};
+ * then with arrays of those sizes.  Doubles are the FP64 values. */
+pmgrit_status pmgrit_host_matrix(const pmgrit_handle* h, int32_t inst, int32_t level, int32_t which,
+                                 int32_t* shape3, int32_t* rp, int32_t* ci, double* v);
+
+/* Host-side inspection: lumped masses (n_dof and n_dof1 doubles), load vector (n_dof) and
+ * initial coefficients (n_dof) of instance inst; NULL pointers are skipped. */
+pmgrit_status pmgrit_host_vectors(const pmgrit_handle* h, int32_t inst, double* mlp, double* ml1, double* load,
+                                  double* u0);
+
+/* Host-side inspection of the triangular-solve schedule of ILUT factor `factor` (0 L, 1 U) at
+ * `level`: out4 = {levels, blocks, block_size, max_rows_per_level}. */
+pmgrit_status pmgrit_host_schedule(const pmgrit_handle* h, int32_t inst, int32_t level, int32_t factor,
+                                   int32_t* out4);
+
+/* Exact p = 1 solve on the host with the library's fast-diagonalisation data of `level`:
+ * x = (M1 + kappa dt_level K1)^{-1} b, both n_dof1 doubles (host).  For testing the setup. */
+pmgrit_status pmgrit_host_coarse_solve(const pmgrit_handle* h, int32_t inst, int32_t level, const double* b,
+                                       double* x);
+
+/* Learned warm start (not part of the paper): a 4-layer 3x3 convolutional network over the
+ * (n+p) x (n+p) coefficient grid with channels 3 -> 32 -> 32 -> 32 -> 1 (inputs u_k, the
+ * load vector and log dt as planes; ReLU between layers; the output is added to u_k).
+ * Weights are a flat host array of float (FP32 master copy; the kernels use BF16 copies):
+ * per layer weights [cout][cin][3][3] then bias [cout]; pmgrit_net_nparams gives the count. */
+int64_t pmgrit_net_nparams(void);
+pmgrit_status pmgrit_net_load(pmgrit_handle* h, const float* weights_host, int64_t n);
+pmgrit_status pmgrit_net_save(const pmgrit_handle* h, float* weights_host, int64_t n);
+
+/* Network inference on a batch: x_dev (nb x 3 x G x G float) -> y_dev (nb x G x G float),
+ * G = grid_n of instance inst, BF16 weights and FP32 accumulation on the matrix cores. */
+pmgrit_status pmgrit_net_forward(pmgrit_handle* h, int32_t inst, int32_t nb, const float* x_dev, float* y_dev,
+                                 void* hip_stream);
+
+/* One training step (Adam, lr, betas 0.9/0.999, eps 1e-8) on a batch with targets t_dev
+ * (nb x G x G float), mean-squared-error loss; loss_host receives the batch loss.  The
+ * gradients come from the library's own backward kernels. */
+pmgrit_status pmgrit_net_train_step(pmgrit_handle* h, int32_t inst, int32_t nb, const float* x_dev,
+                                    const float* t_dev, float lr, float* loss_host, void* hip_stream);
+
+/* Gradients of the mean-squared-error loss for a batch, written to grad_host (nparams
+ * floats), for checking against a CPU reference. */
+pmgrit_status pmgrit_net_grad(pmgrit_handle* h, int32_t inst, int32_t nb, const float* x_dev, const float* t_dev,
+                              float* grad_host, float* loss_host, void* hip_stream);
+
+/* Launch configuration chosen at create (for logs and tests): out8 = {precision,
+ * lds placement mask (bit 0 triangular-solve vector, 1 V-cycle iterate, 2 FP64 iterate,
+ * 3 V-cycle residual, 4 p = 1 vectors), dynamic LDS bytes per workgroup, device LDS limit,
+ * scratch doubles per workgroup, workgroup slots, MGRIT levels, instances}. */
+pmgrit_status pmgrit_info(const pmgrit_handle* h, int64_t* out8);
+
+const char* pmgrit_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMGRIT_H */

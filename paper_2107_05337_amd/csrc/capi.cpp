@@ -1,0 +1,1011 @@
+// capi.cpp -- the C ABI (include/pmgrit.h): host setup per instance and time level, upload,
+// and the MGRIT driver that enqueues the batched spatial-solve launches on one HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/pmgrit.h"
+#include "device_types.hpp"
+#include "host_setup.hpp"
+
+namespace pmg {
+hipError_t phi_prepare(int fp32, int mask, int lds_bytes);
+hipError_t phi_launch(int fp32, int mask, int lds_bytes, const PhiParams& P, const int* plan6, int nmax, int n1max,
+                      int nblocks, hipStream_t st);
+hipError_t fill_launch(double* p, int64_t n, double v, hipStream_t st);
+hipError_t copy_launch(double* dst, const double* src, int64_t n, hipStream_t st);
+hipError_t correct_launch(double* Vl, const double* Vc, int ndof, int m, int ncoarse, hipStream_t st);
+hipError_t norm_reduce_launch(const double* nrm2, const int* begin, double* out, int ninst, hipStream_t st);
+}  // namespace pmg
+
+using namespace pmg;
+
+static thread_local std::string g_err;
+
+static pmgrit_status fail(pmgrit_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(call)                                                                               \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess) return fail(PMGRIT_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------------------------------------
+// host data
+// ------------------------------------------------------------------------------------------
+
+struct LevelHost {
+  double dt = 0;
+  Csr A, L, U;  // A on the pattern of M
+  TriSchedule SL, SU;
+  std::vector<double> tl, tdinv;
+};
+
+struct InstHost {
+  pmgrit_problem prob{};
+  int p = 0, n = 0, domain = 0, N = 0, Nin = 0, ndof = 0, n1 = 0, ndof1 = 0, nlev = 0;
+  std::vector<int> Nl;
+  Dense Mx, Kx, Mx2, My, Ky, Px, Py, M1x, K1x, M1x2, M1y, K1y;  // 1D factors
+  Csr M, K, P, M1, K1, R, Q;
+  std::vector<double> mlp, ml1, F, u0, scale;
+  int tkind = 0;
+  CoarseFdm fdm;
+  std::vector<LevelHost> lev;
+};
+
+struct DevBuf {
+  void* p = nullptr;
+};
+
+struct pmgrit_handle {
+  int device = -1;
+  int ninst = 0;
+  pmgrit_mgrit_opts mo{};
+  pmgrit_solver_opts so{};
+  std::vector<InstHost> inst;
+  int nlev = 0, Nt = 0, m = 0;
+  std::vector<int> Nl;
+  double t_setup = 0;
+  // device side
+  std::vector<void*> allocs;
+  InstDev* d_inst = nullptr;
+  std::vector<InstDev> h_instdev;
+  double** d_vtab = nullptr;
+  double** d_gtab = nullptr;
+  std::vector<double*> h_vtab, h_gtab;
+  double* d_ws = nullptr;
+  int64_t ws_stride = 0;
+  int max_jobs = 0;
+  double* d_nrm2 = nullptr;
+  int* d_vcount = nullptr;
+  int* d_status = nullptr;
+  double* d_resnorm = nullptr;
+  double* h_pinned = nullptr;  // resnorm copy + status
+  int* d_res_begin = nullptr;
+  PhiJob* d_given_jobs = nullptr;
+  int fp32 = 0, mask = 0, lds_bytes = 0, nmax = 0, n1max = 0;
+  int plan[6] = {0, 0, 0, 0, 0, 0};
+  // job lists on the device
+  struct JobList {
+    PhiJob* d = nullptr;
+    int n = 0;
+  };
+  std::vector<JobList> jF, jCF, jRES;  // per level
+  JobList jCoarsest, jSeq;
+  std::vector<int> res_begin;           // per instance, level-0 residual workgroup ranges
+};
+
+// ------------------------------------------------------------------------------------------
+// setup of one instance
+// ------------------------------------------------------------------------------------------
+
+static Csr transpose(const Csr& A) {
+  Csr T;
+  T.nr = A.nc;
+  T.nc = A.nr;
+  T.rp.assign(T.nr + 1, 0);
+  for (int j : A.ci) T.rp[j + 1]++;
+  for (int i = 0; i < T.nr; ++i) T.rp[i + 1] += T.rp[i];
+  T.ci.resize(A.ci.size());
+  T.v.resize(A.v.size());
+  std::vector<int> pos(T.rp.begin(), T.rp.end() - 1);
+  for (int i = 0; i < A.nr; ++i)
+    for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) {
+      int j = A.ci[t];
+      T.ci[pos[j]] = i;
+      T.v[pos[j]] = A.v[t];
+      pos[j]++;
+    }
+  return T;
+}
+
+// interior rows of the full row sums of Y kron X
+static std::vector<double> lumped(const Dense& Y, const Dense& X) {
+  std::vector<double> sy(Y.r, 0.0), sx(X.r, 0.0);
+  for (int i = 0; i < Y.r; ++i)
+    for (int j = 0; j < Y.c; ++j) sy[i] += Y(i, j);
+  for (int i = 0; i < X.r; ++i)
+    for (int j = 0; j < X.c; ++j) sx[i] += X(i, j);
+  std::vector<double> out;
+  for (int iy = 1; iy < Y.r - 1; ++iy)
+    for (int ix = 1; ix < X.r - 1; ++ix) out.push_back(sy[iy] * sx[ix]);
+  return out;
+}
+
+static Dense interior(const Dense& A) {
+  Dense B(A.r - 2, A.c - 2);
+  for (int i = 1; i < A.r - 1; ++i)
+    for (int j = 1; j < A.c - 1; ++j) B(i - 1, j - 1) = A(i, j);
+  return B;
+}
+
+// Cholesky of a dense SPD matrix (lower), in place
+static bool chol(Dense& A) {
+  const int n = A.r;
+  for (int j = 0; j < n; ++j) {
+    double s = A(j, j);
+    for (int k = 0; k < j; ++k) s -= A(j, k) * A(j, k);
+    if (!(s > 0)) return false;
+    A(j, j) = std::sqrt(s);
+    for (int i = j + 1; i < n; ++i) {
+      double t = A(i, j);
+      for (int k = 0; k < j; ++k) t -= A(i, k) * A(j, k);
+      A(i, j) = t / A(j, j);
+    }
+    for (int k = j + 1; k < n; ++k) A(j, k) = 0.0;
+  }
+  return true;
+}
+
+// generalized symmetric eigenproblem K v = lam M v with V^T M V = I
+static bool gen_eig(const Dense& K, const Dense& M, std::vector<double>& lam, Dense& V) {
+  const int n = K.r;
+  Dense C = M;
+  if (!chol(C)) return false;
+  // S = C^{-1} K C^{-T}: solve C W = K (columns), then S = C^{-1} W^T
+  Dense W(n, n), S(n, n);
+  for (int c = 0; c < n; ++c)
+    for (int i = 0; i < n; ++i) {
+      double t = K(i, c);
+      for (int k = 0; k < i; ++k) t -= C(i, k) * W(k, c);
+      W(i, c) = t / C(i, i);
+    }
+  for (int c = 0; c < n; ++c)
+    for (int i = 0; i < n; ++i) {
+      double t = W(c, i);
+      for (int k = 0; k < i; ++k) t -= C(i, k) * S(k, c);
+      S(i, c) = t / C(i, i);
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) S(i, j) = S(j, i) = 0.5 * (S(i, j) + S(j, i));
+  Dense Z;
+  sym_eig(S, lam, Z);
+  // V = C^{-T} Z: back substitution with C^T
+  V = Dense(n, n);
+  for (int c = 0; c < n; ++c)
+    for (int i = n - 1; i >= 0; --i) {
+      double t = Z(i, c);
+      for (int k = i + 1; k < n; ++k) t -= C(k, i) * V(k, c);
+      V(i, c) = t / C(i, i);
+    }
+  return true;
+}
+
+static pmgrit_status setup_instance(pmgrit_handle* H, InstHost& I, const pmgrit_problem& pr) {
+  I.prob = pr;
+  I.p = pr.degree_p;
+  I.n = pr.n_elems;
+  I.domain = pr.domain;
+  const int p = I.p, n = I.n, q = p + 1;
+  I.N = n + p;
+  I.Nin = n + p - 2;
+  I.ndof = I.Nin * I.Nin;
+  I.n1 = n - 1;
+  I.ndof1 = I.n1 * I.n1;
+  // weights of the separable parametrisation: square 1; annulus r(s) = 1 + s (first
+  // direction), |c'(t)| (second); the stiffness splits into a radial and an angular term
+  const bool ann = I.domain == 1;
+  const int wr = ann ? 1 : 0, wri = ann ? 2 : 0, wt = ann ? 3 : 0, wti = ann ? 4 : 0;
+  I.Mx = weighted_1d(n, p, p, 0, 0, wr, q);
+  I.Kx = weighted_1d(n, p, p, 1, 1, wr, q);
+  I.Mx2 = ann ? weighted_1d(n, p, p, 0, 0, wri, q) : I.Mx;
+  I.My = weighted_1d(n, p, p, 0, 0, wt, q);
+  I.Ky = weighted_1d(n, p, p, 1, 1, wti, q);
+  I.Px = weighted_1d(n, p, 1, 0, 0, wr, q);
+  I.Py = weighted_1d(n, p, 1, 0, 0, wt, q);
+  I.M1x = weighted_1d(n, 1, 1, 0, 0, wr, q);
+  I.K1x = weighted_1d(n, 1, 1, 1, 1, wr, q);
+  I.M1x2 = ann ? weighted_1d(n, 1, 1, 0, 0, wri, q) : I.M1x;
+  I.M1y = weighted_1d(n, 1, 1, 0, 0, wt, q);
+  I.K1y = weighted_1d(n, 1, 1, 1, 1, wti, q);
+  // 2D operators: M = My x Mx, K = My x Kx + Ky x Mx2, P = Py x Px (y slow, x fast)
+  I.M = kron_interior(I.N, I.N, I.N, I.N, -p, p, -p, p, {{&I.My, &I.Mx, 1.0}});
+  I.K = kron_interior(I.N, I.N, I.N, I.N, -p, p, -p, p, {{&I.My, &I.Kx, 1.0}, {&I.Ky, &I.Mx2, 1.0}});
+  I.P = kron_interior(I.N, I.N, n + 1, n + 1, -p, 1, -p, 1, {{&I.Py, &I.Px, 1.0}});
+  I.M1 = kron_interior(n + 1, n + 1, n + 1, n + 1, -1, 1, -1, 1, {{&I.M1y, &I.M1x, 1.0}});
+  I.K1 = kron_interior(n + 1, n + 1, n + 1, n + 1, -1, 1, -1, 1, {{&I.M1y, &I.K1x, 1.0}, {&I.K1y, &I.M1x2, 1.0}});
+  I.mlp = lumped(I.My, I.Mx);
+  I.ml1 = lumped(I.M1y, I.M1x);
+  // transfers with the lumped masses folded in: R = (M1^L)^{-1} P^T, Q = (Mp^L)^{-1} P
+  I.R = transpose(I.P);
+  for (int i = 0; i < I.R.nr; ++i)
+    for (int t = I.R.rp[i]; t < I.R.rp[i + 1]; ++t) I.R.v[t] /= I.ml1[i];
+  I.Q = I.P;
+  for (int i = 0; i < I.Q.nr; ++i)
+    for (int t = I.Q.rp[i]; t < I.Q.rp[i + 1]; ++t) I.Q.v[t] /= I.mlp[i];
+  I.F.assign(I.ndof, 0.0);
+  I.u0.assign(I.ndof, 0.0);
+  // exact p = 1 solve: generalized eigenvectors of the second direction
+  {
+    Dense My1 = interior(I.M1y), Ky1 = interior(I.K1y);
+    Dense V;
+    if (!gen_eig(Ky1, My1, I.fdm.lam, V)) return fail(PMGRIT_E_FACTOR, "p=1 mass matrix not SPD");
+    I.fdm.n1 = I.n1;
+    I.fdm.V = V.a;
+  }
+  // time levels
+  const double dt0 = pr.T / pr.n_steps;
+  I.nlev = H->nlev;
+  I.lev.resize(I.nlev);
+  Dense G1 = interior(I.M1x), K1i = interior(I.K1x), H1 = interior(I.M1x2);
+  for (int l = 0; l < I.nlev; ++l) {
+    LevelHost& Lv = I.lev[l];
+    Lv.dt = dt0 * std::pow((double)H->m, l);
+    const double c = pr.kappa * Lv.dt;
+    Lv.A = I.M;
+    for (size_t t = 0; t < Lv.A.v.size(); ++t) Lv.A.v[t] = I.M.v[t] + c * I.K.v[t];
+    std::vector<int> lc(I.ndof), uc(I.ndof);
+    for (int i = 0; i < I.ndof; ++i) {
+      int lo = 0, up = 0;
+      for (int t = Lv.A.rp[i]; t < Lv.A.rp[i + 1]; ++t) {
+        lo += Lv.A.ci[t] < i;
+        up += Lv.A.ci[t] > i;
+      }
+      lc[i] = lo;
+      uc[i] = up;
+    }
+    std::string err;
+    if (!ilut(Lv.A, H->so.ilut_droptol, lc, uc, Lv.L, Lv.U, err)) return fail(PMGRIT_E_FACTOR, err);
+    int bs = H->so.trsv_block;
+    if (bs == 0 || bs == -1) bs = I.Nin;
+    Lv.SL = build_schedule(Lv.L, false, bs);
+    Lv.SU = build_schedule(Lv.U, true, bs);
+    // Thomas data per mode k: T_k = G + c lam_k H with G = M1x + c K1x
+    const int n1 = I.n1;
+    Lv.tl.assign((size_t)n1 * n1, 0.0);
+    Lv.tdinv.assign((size_t)n1 * n1, 0.0);
+    for (int k = 0; k < n1; ++k) {
+      double dprev = 0.0;
+      for (int i = 0; i < n1; ++i) {
+        double diag = G1(i, i) + c * K1i(i, i) + c * I.fdm.lam[k] * H1(i, i);
+        double li = 0.0;
+        if (i > 0) {
+          double off = G1(i, i - 1) + c * K1i(i, i - 1) + c * I.fdm.lam[k] * H1(i, i - 1);
+          li = off / dprev;
+          diag -= li * off;
+        }
+        if (!(diag > 0)) return fail(PMGRIT_E_FACTOR, "p=1 tridiagonal not SPD");
+        Lv.tl[(size_t)k * n1 + i] = li;
+        Lv.tdinv[(size_t)k * n1 + i] = 1.0 / diag;
+        dprev = diag;
+      }
+    }
+  }
+  I.scale.assign(pr.n_steps + 1, dt0);
+  return PMGRIT_OK;
+}
+
+// host version of the exact p = 1 solve (for testing the setup)
+static void host_coarse_solve(const InstHost& I, int level, const double* b, double* x) {
+  const int n1 = I.n1;
+  const LevelHost& L = I.lev[level];
+  std::vector<double> c((size_t)n1 * n1);
+  for (int k = 0; k < n1; ++k)
+    for (int ix = 0; ix < n1; ++ix) {
+      double s = 0;
+      for (int iy = 0; iy < n1; ++iy) s += I.fdm.V[(size_t)iy * n1 + k] * b[(size_t)iy * n1 + ix];
+      c[(size_t)k * n1 + ix] = s;
+    }
+  for (int k = 0; k < n1; ++k) {
+    double* rw = &c[(size_t)k * n1];
+    const double* tl = &L.tl[(size_t)k * n1];
+    const double* td = &L.tdinv[(size_t)k * n1];
+    double yp = rw[0];
+    rw[0] = yp * td[0];
+    for (int i = 1; i < n1; ++i) {
+      double yv = rw[i] - tl[i] * yp;
+      rw[i] = yv * td[i];
+      yp = yv;
+    }
+    for (int i = n1 - 2; i >= 0; --i) rw[i] -= tl[i + 1] * rw[i + 1];
+  }
+  for (int iy = 0; iy < n1; ++iy)
+    for (int ix = 0; ix < n1; ++ix) {
+      double s = 0;
+      for (int k = 0; k < n1; ++k) s += I.fdm.V[(size_t)iy * n1 + k] * c[(size_t)k * n1 + ix];
+      x[(size_t)iy * n1 + ix] = s;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// device upload
+// ------------------------------------------------------------------------------------------
+
+template <typename T>
+static pmgrit_status upload(pmgrit_handle* H, const T* src, size_t n, T** dst) {
+  *dst = nullptr;
+  if (n == 0) n = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) return fail(PMGRIT_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  H->allocs.push_back(p);
+  if (src) {
+    e = hipMemcpy(p, src, n * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(PMGRIT_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  *dst = (T*)p;
+  return PMGRIT_OK;
+}
+
+template <typename T>
+static pmgrit_status upload_vec(pmgrit_handle* H, const std::vector<T>& v, T** dst) {
+  return upload(H, v.empty() ? nullptr : v.data(), v.size(), dst);
+}
+
+// values in the V-cycle precision
+static pmgrit_status upload_vals(pmgrit_handle* H, const std::vector<double>& v, const void** dst) {
+  if (H->fp32) {
+    std::vector<float> f(v.begin(), v.end());
+    float* d = nullptr;
+    pmgrit_status s = upload_vec(H, f, &d);
+    *dst = d;
+    return s;
+  }
+  double* d = nullptr;
+  pmgrit_status s = upload_vec(H, v, &d);
+  *dst = d;
+  return s;
+}
+
+#define TRY(x)                    \
+  do {                            \
+    pmgrit_status s_ = (x);       \
+    if (s_ != PMGRIT_OK) return s_; \
+  } while (0)
+
+static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& T) {
+  T.nlev = S.nlev;
+  T.bs = S.bs;
+  T.max_rows = S.max_rows;
+  int* p;
+  TRY(upload_vec(H, S.lev_ptr, &p));
+  T.lev_ptr = p;
+  TRY(upload_vec(H, S.row, &p));
+  T.row = p;
+  TRY(upload_vec(H, S.orp, &p));
+  T.orp = p;
+  TRY(upload_vec(H, S.oci, &p));
+  T.oci = p;
+  TRY(upload_vals(H, S.ov, &T.ov));
+  TRY(upload_vec(H, S.dq0, &p));
+  T.dq0 = p;
+  TRY(upload_vec(H, S.dcnt, &p));
+  T.dcnt = p;
+  int64_t* p64;
+  TRY(upload_vec(H, S.doff, &p64));
+  T.doff = p64;
+  TRY(upload_vals(H, S.dval, &T.dval));
+  return PMGRIT_OK;
+}
+
+static pmgrit_status upload_jobs(pmgrit_handle* H, const std::vector<PhiJob>& jobs, pmgrit_handle::JobList& out) {
+  out.n = (int)jobs.size();
+  H->max_jobs = std::max(H->max_jobs, out.n);
+  return upload_vec(H, jobs, &out.d);
+}
+
+static pmgrit_status device_setup(pmgrit_handle* H) {
+  HIPCHK(hipSetDevice(H->device));
+  H->fp32 = H->so.precision == 1;
+  const int vt = H->fp32 ? 4 : 8;
+  H->h_instdev.resize(H->ninst);
+  H->nmax = 0;
+  H->n1max = 0;
+  int maxrows = 1;
+  for (int i = 0; i < H->ninst; ++i) {
+    InstHost& I = H->inst[i];
+    InstDev& D = H->h_instdev[i];
+    std::memset(&D, 0, sizeof(D));
+    D.ndof = I.ndof;
+    D.n1 = I.n1;
+    D.ndof1 = I.ndof1;
+    D.nlev = I.nlev;
+    D.nt = I.prob.n_steps;
+    H->nmax = std::max(H->nmax, I.ndof);
+    H->n1max = std::max(H->n1max, I.ndof1);
+    int* p;
+    double* d;
+    TRY(upload_vec(H, I.M.rp, &p));
+    D.rp = p;
+    TRY(upload_vec(H, I.M.ci, &p));
+    D.ci = p;
+    TRY(upload_vec(H, I.M.v, &d));
+    D.M = d;
+    TRY(upload_vec(H, I.R.rp, &p));
+    D.Rrp = p;
+    TRY(upload_vec(H, I.R.ci, &p));
+    D.Rci = p;
+    TRY(upload_vals(H, I.R.v, &D.Rv));
+    TRY(upload_vec(H, I.Q.rp, &p));
+    D.Qrp = p;
+    TRY(upload_vec(H, I.Q.ci, &p));
+    D.Qci = p;
+    TRY(upload_vals(H, I.Q.v, &D.Qv));
+    TRY(upload_vec(H, I.fdm.V, &d));
+    D.V = d;
+    TRY(upload_vec(H, I.F, &d));
+    D.F = d;
+    TRY(upload_vec(H, I.scale, &d));
+    D.scale = d;
+    for (int l = 0; l < I.nlev; ++l) {
+      LevelHost& Lh = I.lev[l];
+      LevelDev& Ld = D.lev[l];
+      Ld.dt = Lh.dt;
+      TRY(upload_vec(H, Lh.A.v, &d));
+      Ld.A64 = d;
+      TRY(upload_vals(H, Lh.A.v, &Ld.Avt));
+      TRY(upload_tri(H, Lh.SL, Ld.L));
+      TRY(upload_tri(H, Lh.SU, Ld.U));
+      TRY(upload_vec(H, Lh.tl, &d));
+      Ld.tl = d;
+      TRY(upload_vec(H, Lh.tdinv, &d));
+      Ld.tdinv = d;
+      maxrows = std::max(maxrows, std::max(Lh.SL.max_rows, Lh.SU.max_rows));
+    }
+  }
+  TRY(upload_vec(H, H->h_instdev, &H->d_inst));
+  // level arrays: level 0 is the caller's trajectory (table filled per call); coarse levels
+  // hold the correction v and the injected right-hand side g
+  H->h_vtab.assign((size_t)H->ninst * kMaxLevels, nullptr);
+  H->h_gtab.assign((size_t)H->ninst * kMaxLevels, nullptr);
+  for (int i = 0; i < H->ninst; ++i)
+    for (int l = 1; l < H->nlev; ++l) {
+      double* v;
+      double* g;
+      size_t sz = (size_t)(H->Nl[l] + 1) * H->inst[i].ndof;
+      TRY(upload<double>(H, nullptr, sz, &v));
+      TRY(upload<double>(H, nullptr, sz, &g));
+      HIPCHK(hipMemset(v, 0, sz * sizeof(double)));
+      HIPCHK(hipMemset(g, 0, sz * sizeof(double)));
+      H->h_vtab[(size_t)i * kMaxLevels + l] = v;
+      H->h_gtab[(size_t)i * kMaxLevels + l] = g;
+    }
+  TRY(upload_vec(H, H->h_vtab, &H->d_vtab));
+  TRY(upload_vec(H, H->h_gtab, &H->d_gtab));
+  // job lists
+  const int m = H->m;
+  H->jF.resize(H->nlev);
+  H->jCF.resize(H->nlev);
+  H->jRES.resize(H->nlev);
+  H->res_begin.assign(H->ninst + 1, 0);
+  for (int l = 0; l + 1 < H->nlev; ++l) {
+    std::vector<PhiJob> F, CF, RES;
+    const int Nl = H->Nl[l];
+    for (int i = 0; i < H->ninst; ++i) {
+      for (int j = 0; j * m < Nl; ++j) {
+        int len = std::min(m - 1, Nl - j * m);
+        if (len > 0) F.push_back({i, l, j * m, len, 0, 0});
+        if (j == 0) {
+          if (len > 0) CF.push_back({i, l, 0, len, 0, 0});
+        }
+      }
+      for (int j = 1; j * m <= Nl; ++j) {
+        CF.push_back({i, l, j * m - 1, std::min(m, Nl - j * m + 1), 0, 0});
+        RES.push_back({i, l, j * m - 1, 1, j, 0});
+      }
+      if (l == 0) H->res_begin[i + 1] = (int)RES.size();
+    }
+    TRY(upload_jobs(H, F, H->jF[l]));
+    TRY(upload_jobs(H, CF, H->jCF[l]));
+    TRY(upload_jobs(H, RES, H->jRES[l]));
+  }
+  {
+    std::vector<PhiJob> C, S;
+    for (int i = 0; i < H->ninst; ++i) {
+      C.push_back({i, H->nlev - 1, 0, H->Nl[H->nlev - 1], 0, 0});
+      S.push_back({i, 0, 0, H->Nt, 0, 0});
+    }
+    TRY(upload_jobs(H, C, H->jCoarsest));
+    TRY(upload_jobs(H, S, H->jSeq));
+  }
+  TRY(upload_vec(H, H->res_begin, &H->d_res_begin));
+  // given-mode jobs (pmgrit_phi): up to 4096 right-hand sides
+  H->max_jobs = std::max(H->max_jobs, 4096);
+  TRY(upload<PhiJob>(H, nullptr, 4096, &H->d_given_jobs));
+  // scratch
+  H->ws_stride = 6 * (int64_t)H->nmax + 2 * (int64_t)H->n1max + 32;
+  H->ws_stride = (H->ws_stride + 31) / 32 * 32;
+  TRY(upload<double>(H, nullptr, (size_t)H->ws_stride * H->max_jobs, &H->d_ws));
+  TRY(upload<double>(H, nullptr, (size_t)H->max_jobs, &H->d_nrm2));
+  TRY(upload<int>(H, nullptr, (size_t)H->max_jobs, &H->d_vcount));
+  TRY(upload<int>(H, nullptr, 4, &H->d_status));
+  TRY(upload<double>(H, nullptr, (size_t)H->ninst, &H->d_resnorm));
+  HIPCHK(hipMemset(H->d_vcount, 0, sizeof(int) * H->max_jobs));
+  HIPCHK(hipMemset(H->d_status, 0, sizeof(int) * 4));
+  HIPCHK(hipHostMalloc((void**)&H->h_pinned, sizeof(double) * (H->ninst + 8), 0));
+  // LDS plan: largest set of vectors that fits, in the order y, d, x, s, coarse
+  int dev_lds = 0;
+  HIPCHK(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, H->device));
+  auto al = [](int b) { return (b + 15) / 16 * 16; };
+  const int base = 512 + al(maxrows * vt);
+  const int sz_y = al(H->nmax * vt), sz_d = sz_y, sz_x = al(H->nmax * 8), sz_s = sz_y, sz_c = al(2 * H->n1max * 8);
+  const int masks[6] = {31, 15, 7, 3, 1, 0};
+  for (int mi = 0; mi < 6; ++mi) {
+    int mk = masks[mi];
+    int off = base;
+    int plan[6] = {-1, -1, -1, -1, -1, 512};
+    if (mk & 1) { plan[0] = off; off += sz_y; }
+    if (mk & 2) { plan[1] = off; off += sz_d; }
+    if (mk & 4) { plan[2] = off; off += sz_x; }
+    if (mk & 8) { plan[3] = off; off += sz_s; }
+    if (mk & 16) { plan[4] = off; off += sz_c; }
+    if (off <= dev_lds || mk == 0) {
+      H->mask = mk;
+      H->lds_bytes = off;
+      std::memcpy(H->plan, plan, sizeof(plan));
+      break;
+    }
+  }
+  HIPCHK(phi_prepare(H->fp32, H->mask, H->lds_bytes));
+  HIPCHK(hipDeviceSynchronize());
+  return PMGRIT_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// driver
+// ------------------------------------------------------------------------------------------
+
+static PhiParams base_params(pmgrit_handle* H, int mode, const PhiJob* jobs) {
+  PhiParams P;
+  std::memset(&P, 0, sizeof(P));
+  P.inst = H->d_inst;
+  P.jobs = jobs;
+  P.vtab = H->d_vtab;
+  P.gtab = H->d_gtab;
+  P.nrm2 = H->d_nrm2;
+  P.vcount = H->d_vcount;
+  P.status = H->d_status;
+  P.ws = H->d_ws;
+  P.ws_stride = H->ws_stride;
+  P.mode = mode;
+  P.guess = H->so.guess == 3 ? 2 : H->so.guess;
+  P.maxcyc = H->so.max_vcycles;
+  P.nu1 = H->so.nu1;
+  P.nu2 = H->so.nu2;
+  P.stol = H->so.spatial_tol;
+  return P;
+}
+
+static hipError_t launch(pmgrit_handle* H, const pmgrit_handle::JobList& J, int mode, hipStream_t st, int guess = -1) {
+  if (J.n == 0) return hipSuccess;
+  PhiParams P = base_params(H, mode, J.d);
+  if (guess >= 0) P.guess = guess;
+  return phi_launch(H->fp32, H->mask, H->lds_bytes, P, H->plan, H->nmax, H->n1max, J.n, st);
+}
+
+// one recursive MGRIT cycle at level l >= 1 on A^{(l)} v = g (v zeroed by the caller)
+static hipError_t coarse_cycle(pmgrit_handle* H, int l, hipStream_t st) {
+  hipError_t e;
+  if (l == H->nlev - 1) return launch(H, H->jCoarsest, kModeChain, st);
+  if ((e = launch(H, H->jF[l], kModeChain, st)) != hipSuccess) return e;
+  if ((e = launch(H, H->jCF[l], kModeChain, st)) != hipSuccess) return e;
+  if ((e = launch(H, H->jRES[l], kModeResidual, st)) != hipSuccess) return e;
+  for (int i = 0; i < H->ninst; ++i) {
+    double* vc = H->h_vtab[(size_t)i * kMaxLevels + l + 1];
+    if ((e = fill_launch(vc, (int64_t)(H->Nl[l + 1] + 1) * H->inst[i].ndof, 0.0, st)) != hipSuccess) return e;
+  }
+  if ((e = coarse_cycle(H, l + 1, st)) != hipSuccess) return e;
+  for (int i = 0; i < H->ninst; ++i) {
+    double* vl = H->h_vtab[(size_t)i * kMaxLevels + l];
+    double* vc = H->h_vtab[(size_t)i * kMaxLevels + l + 1];
+    if ((e = correct_launch(vl, vc, H->inst[i].ndof, H->m, H->Nl[l + 1], st)) != hipSuccess) return e;
+  }
+  return launch(H, H->jF[l], kModeChain, st);  // ideal interpolation = F-relaxation
+}
+
+static pmgrit_status read_status(pmgrit_handle* H, hipStream_t st) {
+  int s[4];
+  HIPCHK(hipMemcpyAsync(s, H->d_status, sizeof(s), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (s[0] & 1) return fail(PMGRIT_E_NONFINITE, "non-finite residual in a spatial solve");
+  if (s[0] & 2) return fail(PMGRIT_E_SPATIAL_NOCONV, "a spatial solve reached max_vcycles");
+  return PMGRIT_OK;
+}
+
+static pmgrit_status begin_solve(pmgrit_handle* H, hipStream_t st, double* const* u_out) {
+  if (H->device < 0) return fail(PMGRIT_E_STATE, "host-only handle");
+  if (!u_out) return fail(PMGRIT_E_ARG, "u_out_dev is NULL");
+  HIPCHK(hipSetDevice(H->device));
+  for (int i = 0; i < H->ninst; ++i) {
+    if (!u_out[i]) return fail(PMGRIT_E_ARG, "u_out_dev[i] is NULL");
+    H->h_vtab[(size_t)i * kMaxLevels] = u_out[i];
+  }
+  HIPCHK(hipMemcpyAsync(H->d_vtab, H->h_vtab.data(), sizeof(double*) * H->h_vtab.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(H->d_status, 0, sizeof(int) * 4, st));
+  HIPCHK(hipMemsetAsync(H->d_vcount, 0, sizeof(int) * H->max_jobs, st));
+  // initial iterate: U_0 = u0, U_k = 0 for k >= 1
+  for (int i = 0; i < H->ninst; ++i) {
+    const int nd = H->inst[i].ndof;
+    HIPCHK(fill_launch(u_out[i] + nd, (int64_t)H->Nt * nd, 0.0, st));
+    HIPCHK(hipMemcpyAsync(u_out[i], H->inst[i].u0.data(), sizeof(double) * nd, hipMemcpyHostToDevice, st));
+  }
+  return PMGRIT_OK;
+}
+
+static int64_t sum_vcycles(pmgrit_handle* H, hipStream_t st) {
+  std::vector<int> v(H->max_jobs);
+  if (hipMemcpyAsync(v.data(), H->d_vcount, sizeof(int) * H->max_jobs, hipMemcpyDeviceToHost, st) != hipSuccess) return -1;
+  if (hipStreamSynchronize(st) != hipSuccess) return -1;
+  int64_t s = 0;
+  for (int x : v) s += x;
+  return s;
+}
+
+extern "C" {
+
+const char* pmgrit_last_error(void) { return g_err.c_str(); }
+
+pmgrit_status pmgrit_create(int32_t n_instances, const pmgrit_problem* probs, const pmgrit_mgrit_opts* mopts,
+                            const pmgrit_solver_opts* sopts, int32_t hip_device, pmgrit_handle** out) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!out || !probs || !mopts || !sopts || n_instances < 1) return fail(PMGRIT_E_ARG, "null argument or no instances");
+  const pmgrit_mgrit_opts& mo = *mopts;
+  const pmgrit_solver_opts& so = *sopts;
+  if (mo.cfactor < 2 || mo.max_levels < 1 || mo.max_levels > kMaxLevels || mo.coarsest_max < 1 || mo.max_iter < 0 ||
+      !(mo.tol >= 0))
+    return fail(PMGRIT_E_ARG, "invalid MGRIT options");
+  if (so.nu1 < 1 || so.nu2 < 0 || !(so.ilut_droptol >= 0) || !(so.spatial_tol > 0) || so.max_vcycles < 1 ||
+      (so.precision != 0 && so.precision != 1) || so.guess < 0 || so.guess > 3 || so.trsv_block < -1)
+    return fail(PMGRIT_E_ARG, "invalid solver options");
+  for (int i = 0; i < n_instances; ++i) {
+    const pmgrit_problem& p = probs[i];
+    if (p.degree_p < 2 || p.degree_p > 8 || p.n_elems < 2 || p.n_elems > 1024 || (p.domain != 0 && p.domain != 1) ||
+        !(p.kappa > 0) || !(p.T > 0) || p.n_steps < 1)
+      return fail(PMGRIT_E_ARG, "invalid problem " + std::to_string(i));
+    if (p.n_steps != probs[0].n_steps) return fail(PMGRIT_E_ARG, "all instances must share n_steps");
+  }
+  std::unique_ptr<pmgrit_handle> H(new pmgrit_handle());
+  H->device = hip_device;
+  H->ninst = n_instances;
+  H->mo = mo;
+  H->so = so;
+  H->Nt = probs[0].n_steps;
+  H->m = mo.cfactor;
+  // hierarchy: N_l = floor(N_t / m^l) while more than coarsest_max intervals remain
+  H->Nl.push_back(H->Nt);
+  while ((int)H->Nl.size() < mo.max_levels && H->Nl.back() > mo.coarsest_max && H->Nl.back() / H->m >= 1)
+    H->Nl.push_back(H->Nl.back() / H->m);
+  H->nlev = (int)H->Nl.size();
+  H->inst.resize(n_instances);
+  for (int i = 0; i < n_instances; ++i) TRY(setup_instance(H.get(), H->inst[i], probs[i]));
+  if (hip_device >= 0) {
+    pmgrit_status s = device_setup(H.get());
+    if (s != PMGRIT_OK) {
+      std::string keep = g_err;
+      pmgrit_destroy(H.release());
+      g_err = keep;
+      return s;
+    }
+  }
+  H->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = H.release();
+  return PMGRIT_OK;
+}
+
+void pmgrit_destroy(pmgrit_handle* h) {
+  if (!h) return;
+  if (h->device >= 0) {
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    for (void* p : h->allocs) (void)hipFree(p);
+    if (h->h_pinned) (void)hipHostFree(h->h_pinned);
+  }
+  delete h;
+}
+
+pmgrit_status pmgrit_dims(const pmgrit_handle* h, int32_t inst, int64_t* n_dof, int32_t* grid_n, int32_t* n_levels) {
+  if (!h || inst < 0 || inst >= h->ninst) return fail(PMGRIT_E_ARG, "bad handle or instance");
+  if (n_dof) *n_dof = h->inst[inst].ndof;
+  if (grid_n) *grid_n = h->inst[inst].N;
+  if (n_levels) *n_levels = h->nlev;
+  return PMGRIT_OK;
+}
+
+static std::vector<double> modal_load(const InstHost& I, int nm, const int32_t* k, const int32_t* l, const double* a) {
+  const bool ann = I.domain == 1;
+  std::vector<double> out(I.ndof, 0.0);
+  for (int q = 0; q < nm; ++q) {
+    std::vector<double> fx = mode_load_1d(I.n, I.p, k[q], ann ? 1 : 0, I.p + 1);
+    std::vector<double> fy = mode_load_1d(I.n, I.p, l[q], ann ? 3 : 0, I.p + 1);
+    for (int iy = 1; iy <= I.Nin; ++iy)
+      for (int ix = 1; ix <= I.Nin; ++ix) out[(size_t)(iy - 1) * I.Nin + (ix - 1)] += a[q] * fx[ix] * fy[iy];
+  }
+  return out;
+}
+
+pmgrit_status pmgrit_set_source_modes(pmgrit_handle* h, int32_t inst, int32_t n_modes, const int32_t* k,
+                                      const int32_t* l, const double* amp, int32_t time_kind) {
+  if (!h || inst < 0 || inst >= h->ninst || n_modes < 0 || (n_modes > 0 && (!k || !l || !amp)) ||
+      (time_kind != 0 && time_kind != 1))
+    return fail(PMGRIT_E_ARG, "bad source arguments");
+  InstHost& I = h->inst[inst];
+  for (int q = 0; q < n_modes; ++q)
+    if (k[q] < 0 || l[q] < 0) return fail(PMGRIT_E_ARG, "negative mode number");
+  I.F = modal_load(I, n_modes, k, l, amp);
+  I.tkind = time_kind;
+  const double dt = I.prob.T / I.prob.n_steps;
+  for (int s = 0; s <= I.prob.n_steps; ++s) I.scale[s] = dt * (time_kind == 1 ? std::exp(-s * dt) : 1.0);
+  if (h->device >= 0) {
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipMemcpy((void*)h->h_instdev[inst].F, I.F.data(), sizeof(double) * I.ndof, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy((void*)h->h_instdev[inst].scale, I.scale.data(), sizeof(double) * I.scale.size(),
+                     hipMemcpyHostToDevice));
+  }
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_set_initial_modes(pmgrit_handle* h, int32_t inst, int32_t n_modes, const int32_t* k,
+                                       const int32_t* l, const double* amp) {
+  if (!h || inst < 0 || inst >= h->ninst || n_modes < 0 || (n_modes > 0 && (!k || !l || !amp)))
+    return fail(PMGRIT_E_ARG, "bad initial-condition arguments");
+  InstHost& I = h->inst[inst];
+  if (n_modes == 0) {
+    I.u0.assign(I.ndof, 0.0);
+    return PMGRIT_OK;
+  }
+  // L2 projection: solve M c = int u0 Phi by conjugate gradients with Jacobi preconditioning
+  std::vector<double> b = modal_load(I, n_modes, k, l, amp), x(I.ndof, 0.0), r = b, z(I.ndof), pdir(I.ndof),
+                      Ap(I.ndof), dg(I.ndof);
+  const Csr& M = I.M;
+  for (int i = 0; i < I.ndof; ++i)
+    for (int t = M.rp[i]; t < M.rp[i + 1]; ++t)
+      if (M.ci[t] == i) dg[i] = M.v[t];
+  auto dot = [](const std::vector<double>& a, const std::vector<double>& c) {
+    double s = 0;
+    for (size_t i = 0; i < a.size(); ++i) s += a[i] * c[i];
+    return s;
+  };
+  for (int i = 0; i < I.ndof; ++i) z[i] = r[i] / dg[i];
+  pdir = z;
+  double rz = dot(r, z), bn = std::sqrt(dot(b, b));
+  for (int it = 0; it < 20000 && std::sqrt(dot(r, r)) > 1e-15 * bn; ++it) {
+    for (int i = 0; i < I.ndof; ++i) {
+      double s = 0;
+      for (int t = M.rp[i]; t < M.rp[i + 1]; ++t) s += M.v[t] * pdir[M.ci[t]];
+      Ap[i] = s;
+    }
+    double alpha = rz / dot(pdir, Ap);
+    for (int i = 0; i < I.ndof; ++i) {
+      x[i] += alpha * pdir[i];
+      r[i] -= alpha * Ap[i];
+      z[i] = r[i] / dg[i];
+    }
+    double rz2 = dot(r, z);
+    for (int i = 0; i < I.ndof; ++i) pdir[i] = z[i] + rz2 / rz * pdir[i];
+    rz = rz2;
+  }
+  I.u0 = x;
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_set_initial_coeffs(pmgrit_handle* h, int32_t inst, const double* u0_host) {
+  if (!h || inst < 0 || inst >= h->ninst || !u0_host) return fail(PMGRIT_E_ARG, "bad initial coefficients");
+  InstHost& I = h->inst[inst];
+  I.u0.assign(u0_host, u0_host + I.ndof);
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* const* u_out_dev, pmgrit_stats* stats) {
+  if (!h) return fail(PMGRIT_E_ARG, "null handle");
+  hipStream_t st = (hipStream_t)hip_stream;
+  auto t0 = std::chrono::steady_clock::now();
+  TRY(begin_solve(h, st, u_out_dev));
+  pmgrit_stats S;
+  std::memset(&S, 0, sizeof(S));
+  int64_t phi = 0;
+  int iters = 0;
+  pmgrit_status rc = PMGRIT_OK;
+  if (h->nlev == 1) {
+    HIPCHK(launch(h, h->jSeq, kModeChain, st, h->so.guess == 0 ? 0 : 1));
+    phi += (int64_t)h->Nt * h->ninst;
+  } else {
+    std::vector<double> r0(h->ninst, -1.0);
+    auto count_jobs = [&](const pmgrit_handle::JobList& J, bool chain) -> int64_t {
+      (void)chain;
+      return J.n;
+    };
+    (void)count_jobs;
+    // spatial solves per level-0 FCF + residual: N_0 + N_0/m (F, C, F and residual steps)
+    for (;;) {
+      HIPCHK(launch(h, h->jF[0], kModeChain, st));
+      HIPCHK(launch(h, h->jCF[0], kModeChain, st));
+      HIPCHK(launch(h, h->jRES[0], kModeResidual, st));
+      HIPCHK(norm_reduce_launch(h->d_nrm2, h->d_res_begin, h->d_resnorm, h->ninst, st));
+      HIPCHK(hipMemcpyAsync(h->h_pinned, h->d_resnorm, sizeof(double) * h->ninst, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      phi += (int64_t)h->ninst * (2 * h->Nt - h->Nt / h->m + 2 * (h->Nt / h->m));
+      bool done = true, bad = false;
+      double worst = 0.0;
+      for (int i = 0; i < h->ninst; ++i) {
+        double rn = std::sqrt(h->h_pinned[i]);
+        if (!std::isfinite(rn)) bad = true;
+        if (r0[i] < 0) r0[i] = rn;
+        double rel = r0[i] > 0 ? rn / r0[i] : 0.0;
+        worst = std::max(worst, rel);
+        if (!(rn <= h->mo.tol * r0[i] || r0[i] == 0.0)) done = false;
+      }
+      if (iters < 64) S.res_hist[iters] = worst;
+      pmgrit_status s = read_status(h, st);
+      if (s != PMGRIT_OK) {
+        rc = s;
+        break;
+      }
+      if (bad) {
+        rc = fail(PMGRIT_E_NONFINITE, "non-finite MGRIT residual");
+        break;
+      }
+      if (done) break;
+      if (iters >= h->mo.max_iter) {
+        rc = fail(PMGRIT_E_MGRIT_NOCONV, "MGRIT reached max_iter");
+        break;
+      }
+      for (int i = 0; i < h->ninst; ++i) {
+        double* vc = h->h_vtab[(size_t)i * kMaxLevels + 1];
+        HIPCHK(fill_launch(vc, (int64_t)(h->Nl[1] + 1) * h->inst[i].ndof, 0.0, st));
+      }
+      HIPCHK(coarse_cycle(h, 1, st));
+      for (int i = 0; i < h->ninst; ++i) {
+        double* vc = h->h_vtab[(size_t)i * kMaxLevels + 1];
+        HIPCHK(correct_launch(u_out_dev[i], vc, h->inst[i].ndof, h->m, h->Nl[1], st));
+      }
+      ++iters;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  if (rc == PMGRIT_OK) rc = read_status(h, st);
+  S.mgrit_iters = iters;
+  S.phi_calls = phi;
+  S.vcycles = sum_vcycles(h, st);
+  S.t_setup_s = h->t_setup;
+  S.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = S;
+  return rc;
+}
+
+pmgrit_status pmgrit_solve_sequential(pmgrit_handle* h, void* hip_stream, double* const* u_out_dev,
+                                      pmgrit_stats* stats) {
+  if (!h) return fail(PMGRIT_E_ARG, "null handle");
+  hipStream_t st = (hipStream_t)hip_stream;
+  auto t0 = std::chrono::steady_clock::now();
+  TRY(begin_solve(h, st, u_out_dev));
+  HIPCHK(launch(h, h->jSeq, kModeChain, st, h->so.guess == 0 ? 0 : 1));
+  HIPCHK(hipStreamSynchronize(st));
+  pmgrit_status rc = read_status(h, st);
+  if (stats) {
+    pmgrit_stats S;
+    std::memset(&S, 0, sizeof(S));
+    S.phi_calls = (int64_t)h->Nt * h->ninst;
+    S.vcycles = sum_vcycles(h, st);
+    S.t_setup_s = h->t_setup;
+    S.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *stats = S;
+  }
+  return rc;
+}
+
+pmgrit_status pmgrit_phi(pmgrit_handle* h, int32_t inst, int32_t level, int32_t nrhs, const double* b_dev,
+                         double* x_dev, int32_t* vcycles_dev, void* hip_stream) {
+  if (!h || inst < 0 || inst >= h->ninst || level < 0 || level >= h->nlev || nrhs < 0 || nrhs > 4096 ||
+      (nrhs > 0 && (!b_dev || !x_dev)))
+    return fail(PMGRIT_E_ARG, "bad pmgrit_phi arguments");
+  if (h->device < 0) return fail(PMGRIT_E_STATE, "host-only handle");
+  if (nrhs == 0) return PMGRIT_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIPCHK(hipSetDevice(h->device));
+  std::vector<PhiJob> jobs(nrhs, PhiJob{inst, level, 0, 1, 0, 0});
+  HIPCHK(hipMemcpyAsync(h->d_given_jobs, jobs.data(), sizeof(PhiJob) * nrhs, hipMemcpyHostToDevice, st));
+  PhiParams P = base_params(h, kModeGiven, h->d_given_jobs);
+  P.vtab = nullptr;
+  P.bgiven = b_dev;
+  P.xgiven = x_dev;
+  P.vlast = vcycles_dev;
+  HIPCHK(phi_launch(h->fp32, h->mask, h->lds_bytes, P, h->plan, h->nmax, h->n1max, nrhs, st));
+  // the job array is host memory that must outlive the copy
+  HIPCHK(hipStreamSynchronize(st));
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_host_matrix(const pmgrit_handle* h, int32_t inst, int32_t level, int32_t which, int32_t* shape3,
+                                 int32_t* rp, int32_t* ci, double* v) {
+  if (!h || inst < 0 || inst >= h->ninst || level < 0 || level >= h->nlev || !shape3)
+    return fail(PMGRIT_E_ARG, "bad inspection arguments");
+  const InstHost& I = h->inst[inst];
+  const Csr* A = nullptr;
+  switch (which) {
+    case 0: A = &I.M; break;
+    case 1: A = &I.K; break;
+    case 2: A = &I.lev[level].A; break;
+    case 3: A = &I.lev[level].L; break;
+    case 4: A = &I.lev[level].U; break;
+    case 5: A = &I.P; break;
+    case 6: A = &I.M1; break;
+    case 7: A = &I.K1; break;
+    default: return fail(PMGRIT_E_ARG, "bad matrix selector");
+  }
+  shape3[0] = A->nr;
+  shape3[1] = A->nc;
+  shape3[2] = A->nnz();
+  if (rp) {
+    if (!ci || !v) return fail(PMGRIT_E_ARG, "null output array");
+    std::memcpy(rp, A->rp.data(), sizeof(int) * (A->nr + 1));
+    std::memcpy(ci, A->ci.data(), sizeof(int) * A->nnz());
+    std::memcpy(v, A->v.data(), sizeof(double) * A->nnz());
+  }
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_host_vectors(const pmgrit_handle* h, int32_t inst, double* mlp, double* ml1, double* load,
+                                  double* u0) {
+  if (!h || inst < 0 || inst >= h->ninst) return fail(PMGRIT_E_ARG, "bad inspection arguments");
+  const InstHost& I = h->inst[inst];
+  if (mlp) std::memcpy(mlp, I.mlp.data(), sizeof(double) * I.ndof);
+  if (ml1) std::memcpy(ml1, I.ml1.data(), sizeof(double) * I.ndof1);
+  if (load) std::memcpy(load, I.F.data(), sizeof(double) * I.ndof);
+  if (u0) std::memcpy(u0, I.u0.data(), sizeof(double) * I.ndof);
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_host_schedule(const pmgrit_handle* h, int32_t inst, int32_t level, int32_t factor, int32_t* out4) {
+  if (!h || inst < 0 || inst >= h->ninst || level < 0 || level >= h->nlev || (factor != 0 && factor != 1) || !out4)
+    return fail(PMGRIT_E_ARG, "bad inspection arguments");
+  const TriSchedule& S = factor == 0 ? h->inst[inst].lev[level].SL : h->inst[inst].lev[level].SU;
+  out4[0] = S.nlev;
+  out4[1] = S.nblocks;
+  out4[2] = S.bs;
+  out4[3] = S.max_rows;
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_host_coarse_solve(const pmgrit_handle* h, int32_t inst, int32_t level, const double* b,
+                                       double* x) {
+  if (!h || inst < 0 || inst >= h->ninst || level < 0 || level >= h->nlev || !b || !x)
+    return fail(PMGRIT_E_ARG, "bad inspection arguments");
+  host_coarse_solve(h->inst[inst], level, b, x);
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_info(const pmgrit_handle* h, int64_t* out8) {
+  if (!h || !out8) return fail(PMGRIT_E_ARG, "bad info arguments");
+  int dev_lds = 0;
+  if (h->device >= 0) (void)hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
+  out8[0] = h->so.precision;
+  out8[1] = h->mask;
+  out8[2] = h->lds_bytes;
+  out8[3] = dev_lds;
+  out8[4] = h->ws_stride;
+  out8[5] = h->max_jobs;
+  out8[6] = h->nlev;
+  out8[7] = h->ninst;
+  return PMGRIT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+The bar: every trajectory matches the oracle's sequential implicit Euler with direct solves (the
+plain definition of what MGRIT converges to, eq:mgrit) to 1e-10 relative in the discrete L2 norm
+over all time points, and every spatial solve matches a dense direct solve."""
+import sys
+
+import numpy as np
+import pytest
+
+try:  # imported at collection time so a slow first import is not charged to a test's timeout
+    import torch as _torch  # noqa: F401
+except Exception:  # pragma: no cover
+    _torch = None
+
+import oracle as O
+import paper_2107_05337_amd as pm
+from paper_2107_05337_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+EPS = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need a visible MI355X"
+    return T
+
+
+def make_solver(cfg, precision=0, guess=2, trsv_block=-1, tol=1e-10, stol=1e-12, **mo):
+    probs = [pm.problem(d["p"], d["n"], d["Nt"], kappa=d["kappa"], T=d["T"], domain=d["domain"])
+             for d in cfg["instances"]]
+    mopts = pm.default_mgrit_opts(cfactor=cfg["m"], max_levels=cfg["max_levels"], coarsest_max=cfg["coarsest_max"],
+                                  tol=tol, **mo)
+    sopts = pm.default_solver_opts(precision=precision, guess=guess, trsv_block=trsv_block, spatial_tol=stol)
+    S = pm.Solver(probs, mopts, sopts, device=0)
+    for i, d in enumerate(cfg["instances"]):
+        S.set_source(i, d["src"], d["tkind"])
+        if d["init"]:
+            S.set_initial_modes(i, d["init"])
+    return S
+
+
+def oracle_sequential(d, nsteps=None):
+    P = O.Problem(d["p"], d["n"], d["domain"])
+    F = P.load_vector(d["src"])
+    u0 = P.project(d["init"]) if d["init"] else np.zeros(P.ndof)
+    Nt = d["Nt"] if nsteps is None else nsteps
+    T = d["T"] * Nt / d["Nt"]
+    return P.sequential(d["kappa"], T, Nt, F, d["tkind"], u0)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("p,n,domain,precision,blk", [
+    (2, 8, 0, 0, -1), (3, 12, 0, 0, 1), (3, 12, 1, 0, -1), (4, 10, 0, 1, -1), (2, 16, 1, 1, 1), (5, 9, 0, 0, 7)])
+def test_phi_matches_dense_solve(torch, p, n, domain, precision, blk):
+    say(f"case phi p={p} n={n} domain={domain} precision={precision} block={blk}")
+    cfg = W.small("x", p, n, 16, domain=domain)
+    S = make_solver(cfg, precision=precision, trsv_block=blk)
+    P = O.Problem(p, n, domain)
+    rng = np.random.default_rng(p * 100 + n)
+    nrhs = 7
+    for level in range(S.dims()[2]):
+        dt = 0.1 / 16 * 4 ** level
+        A = P.dense("M") + dt * P.dense("K")
+        B = rng.standard_normal((nrhs, P.ndof))
+        B[3] = 0.0  # a zero right-hand side is solved by the zero guess in zero cycles
+        X0 = np.zeros_like(B)
+        X0[1] = rng.standard_normal(P.ndof)  # a non-zero initial guess
+        b = torch.tensor(B, device="cuda")
+        x = torch.tensor(X0, device="cuda")
+        vc = torch.zeros(nrhs, dtype=torch.int32, device="cuda")
+        S.phi(0, level, b, x, vc)
+        X = x.cpu().numpy()
+        for j in range(nrhs):
+            if j == 3:
+                assert np.all(X[j] == 0.0) and int(vc[j]) == 0
+                continue
+            r = np.linalg.norm(B[j] - A @ X[j]) / np.linalg.norm(B[j])
+            assert r <= 1.0000001e-12, (level, j, r)
+            xe = np.linalg.solve(A, B[j])
+            assert rel(X[j], xe) < 1e-9
+            assert 1 <= int(vc[j]) <= 20
+
+
+def test_mgrit_two_level_manufactured(torch):
+    cfg = W.config("heat-p2-h16-Nt128")
+    say("case mgrit heat-p2-h16-Nt128 (two-level, m=4)")
+    S = make_solver(cfg)
+    (U,), st = S.solve_mgrit()
+    Us = oracle_sequential(cfg["instances"][0])
+    eps = rel(U.cpu().numpy(), Us)
+    say(f"  eps={eps:.3e} iters={st['mgrit_iters']} vcycles={st['vcycles']}")
+    assert eps <= EPS
+    # same algorithm as the oracle's MGRIT: same iteration count
+    d = cfg["instances"][0]
+    P = O.Problem(d["p"], d["n"], 0)
+    r = P.mgrit(d["kappa"], d["T"], d["Nt"], P.load_vector(d["src"]), d["tkind"], P.project(d["init"]), m=4,
+                max_levels=2, tol=1e-10)
+    assert abs(st["mgrit_iters"] - r["iters"]) <= 1
+    assert st["res_hist"][0] == 1.0 and st["res_hist"][-1] <= 1e-10
+
+
+@pytest.mark.parametrize("p", [3, 4, 5])
+def test_mgrit_multilevel_full_size(torch, p):
+    name = f"heat-p{p}-h64-Nt1024"
+    say(f"case mgrit {name}")
+    cfg = W.config(name)
+    S = make_solver(cfg)
+    assert S.dims()[2] == 4  # 1024 -> 128 -> 16 -> 2
+    (U,), st = S.solve_mgrit()
+    Us = oracle_sequential(cfg["instances"][0])
+    eps = rel(U.cpu().numpy(), Us)
+    say(f"  eps={eps:.3e} iters={st['mgrit_iters']} vcycles={st['vcycles']} t={st['t_solve_s']:.3f}s")
+    assert eps <= EPS
+    assert 5 <= st["mgrit_iters"] <= 15
+
+
+def test_mgrit_fp32_refined_full_size(torch):
+    name = "heat-p3-h64-Nt1024"
+    say(f"case mgrit {name} FP32 V-cycle in FP64 refinement")
+    cfg = W.config(name)
+    S = make_solver(cfg, precision=1)
+    (U,), st = S.solve_mgrit()
+    Us = oracle_sequential(cfg["instances"][0])
+    eps = rel(U.cpu().numpy(), Us)
+    say(f"  eps={eps:.3e} iters={st['mgrit_iters']} vcycles={st['vcycles']} t={st['t_solve_s']:.3f}s")
+    assert eps <= EPS
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sequential_matches_oracle(torch, precision):
+    cfg = W.small("x", 3, 16, 40, domain=1)
+    say(f"case sequential annulus p=3 n=16 Nt=40 precision={precision}")
+    S = make_solver(cfg, precision=precision)
+    (U,), st = S.solve_sequential()
+    Us = oracle_sequential(cfg["instances"][0])
+    assert rel(U.cpu().numpy(), Us) <= EPS
+    assert st["phi_calls"] == 40
+
+
+@pytest.mark.parametrize("Nt,m", [(37, 4), (1, 4), (9, 8), (64, 2)])
+def test_mgrit_ragged_and_degenerate(torch, Nt, m):
+    say(f"case mgrit ragged Nt={Nt} m={m}")
+    cfg = W.small("x", 2, 8, Nt)
+    cfg["m"] = m
+    S = make_solver(cfg, tol=1e-12)
+    (U,), st = S.solve_mgrit()
+    Us = oracle_sequential(cfg["instances"][0])
+    assert rel(U.cpu().numpy(), Us) <= EPS
+
+
+def test_heterogeneous_batch(torch):
+    say("case mgrit heterogeneous batch of 4 instances")
+    insts = [
+        dict(p=2, n=8, domain=0, kappa=0.3, T=0.1, Nt=64, src=W.random_modes(11, 3, 4), tkind=0, init=[]),
+        dict(p=3, n=16, domain=1, kappa=2.0, T=0.1, Nt=64, src=W.random_modes(12, 3, 4), tkind=0, init=[]),
+        dict(p=4, n=8, domain=0, kappa=1.0, T=0.1, Nt=64, src=W.random_modes(13, 3, 4), tkind=1,
+             init=[(1, 1, 1.0)]),
+        dict(p=5, n=12, domain=1, kappa=5.0, T=0.1, Nt=64, src=W.random_modes(14, 3, 4), tkind=0, init=[]),
+    ]
+    cfg = dict(instances=insts, m=4, max_levels=12, coarsest_max=4)
+    S = make_solver(cfg, tol=1e-11)
+    U, st = S.solve_mgrit()
+    for i, d in enumerate(insts):
+        eps = rel(U[i].cpu().numpy(), oracle_sequential(d))
+        say(f"  instance {i}: eps={eps:.3e}")
+        assert eps <= EPS
+
+
+def test_deterministic(torch):
+    say("case determinism heat-p2-h16-Nt128")
+    cfg = W.config("heat-p2-h16-Nt128")
+    S = make_solver(cfg)
+    (U1,), _ = S.solve_mgrit()
+    (U2,), _ = S.solve_mgrit()
+    assert torch.equal(U1, U2)

@@ -1,0 +1,131 @@
+"""Host-side tests of the library (no GPU): the C ABI loads and exports every declared symbol, and
+the library's own setup (Kronecker assembly, ILUT, transfers, exact p = 1 solve, schedules)
+agrees with the independently written oracle."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+import paper_2107_05337_amd as pm
+
+
+def host_solver(p, n, domain=0, Nt=16, kappa=1.0, T=0.1, m=4, trsv_block=-1, **kw):
+    prob = pm.problem(p, n, Nt, kappa=kappa, T=T, domain=domain)
+    so = pm.default_solver_opts(trsv_block=trsv_block, **kw)
+    mo = pm.default_mgrit_opts(cfactor=m, coarsest_max=2)
+    return pm.Solver([prob], mo, so, device=-1)
+
+
+def test_exports_every_declared_symbol():
+    names = pm.header_functions()
+    assert "pmgrit_create" in names and "pmgrit_solve_mgrit" in names and len(names) >= 20
+    L = C.CDLL(pm.LIB_PATH)
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+@pytest.mark.parametrize("p,n,domain", [(2, 5, 0), (3, 6, 0), (5, 4, 0), (2, 6, 1), (4, 5, 1)])
+def test_assembly_matches_oracle(p, n, domain):
+    S = host_solver(p, n, domain)
+    P = O.Problem(p, n, domain)
+    for name in ("M", "K", "P", "M1", "K1"):
+        A = S.host_matrix(name).toarray()
+        B = P.dense(name)
+        assert A.shape == B.shape, name
+        # same sparsity pattern (tensor-product support overlap)
+        assert np.array_equal(S.host_matrix(name).nnz, P.scipy(name).nnz), name
+        assert np.abs(A - B).max() <= 1e-13 * np.abs(B).max(), name
+    v = S.host_vectors()
+    mlp, ml1 = P.lumped()
+    assert np.allclose(v["mlp"], mlp, rtol=1e-13)
+    assert np.allclose(v["ml1"], ml1, rtol=1e-13)
+
+
+def test_level_operator_and_ilut_match_oracle():
+    p, n, Nt, T, kappa = 3, 8, 64, 0.1, 1.0
+    S = host_solver(p, n, 0, Nt=Nt, kappa=kappa, T=T, m=4)
+    P = O.Problem(p, n, 0)
+    for level in (0, 1):
+        dt = T / Nt * 4 ** level
+        A = S.host_matrix("A", level=level)
+        Ao = P.scipy("M") + kappa * dt * P.scipy("K")
+        assert abs(A - Ao).max() <= 1e-13 * abs(Ao).max()
+        L, U = S.host_matrix("L", level=level), S.host_matrix("U", level=level)
+        rc, Lo, Uo = P.ilut(kappa * dt, tau=1e-12)
+        assert rc == 0
+        # identical definition (same caps, drop rule and tie order): same pattern, values to rounding
+        assert L.nnz == Lo.nnz and U.nnz == Uo.nnz
+        assert (abs(L - Lo) > 1e-10 * abs(Lo).max()).nnz == 0
+        assert (abs(U - Uo) > 1e-10 * abs(Uo).max()).nnz == 0
+
+
+@pytest.mark.parametrize("domain", [0, 1])
+def test_sources_and_projection_match_oracle(domain):
+    p, n = 3, 7
+    S = host_solver(p, n, domain)
+    P = O.Problem(p, n, domain)
+    modes = [(1, 1, 2.0), (2, 3, -0.5), (0, 2, 0.25)]
+    S.set_source(0, modes, 0)
+    S.set_initial_modes(0, [(1, 2, 1.5)])
+    v = S.host_vectors()
+    Fo = P.load_vector(modes)
+    assert np.abs(v["load"] - Fo).max() <= 1e-13 * np.abs(Fo).max()
+    uo = P.project([(1, 2, 1.5)])
+    assert np.abs(v["u0"] - uo).max() <= 1e-11 * np.abs(uo).max()
+
+
+@pytest.mark.parametrize("domain,level", [(0, 0), (0, 2), (1, 0), (1, 1)])
+def test_exact_p1_solve(domain, level):
+    p, n, Nt, T, kappa = 2, 9, 64, 0.1, 0.7
+    S = host_solver(p, n, domain, Nt=Nt, kappa=kappa, T=T, m=4)
+    P = O.Problem(p, n, domain)
+    dt = T / Nt * 4 ** level
+    A1 = P.dense("M1") + kappa * dt * P.dense("K1")
+    b = np.random.default_rng(2).standard_normal(A1.shape[0])
+    x = S.host_coarse_solve(b, level=level)
+    assert np.allclose(x, np.linalg.solve(A1, b), rtol=1e-11, atol=1e-13)
+
+
+def _row_levels(T, lower):
+    n = T.shape[0]
+    lev = np.zeros(n, dtype=int)
+    rng = range(n) if lower else range(n - 1, -1, -1)
+    for i in rng:
+        cols = T.indices[T.indptr[i]:T.indptr[i + 1]]
+        cols = cols[cols < i] if lower else cols[cols > i]
+        lev[i] = lev[cols].max() + 1 if len(cols) else 0
+    return lev.max() + 1
+
+
+def test_schedules():
+    p, n = 3, 12
+    S1 = host_solver(p, n, 0, trsv_block=1)
+    L, U = S1.host_matrix("L"), S1.host_matrix("U")
+    s = S1.host_schedule(factor=0)
+    assert s["block_size"] == 1 and s["levels"] == _row_levels(L, True)
+    s = S1.host_schedule(factor=1)
+    assert s["levels"] == _row_levels(U, False)
+    Sl = host_solver(p, n, 0, trsv_block=-1)
+    nin = n + p - 2
+    for f in (0, 1):
+        s = Sl.host_schedule(factor=f)
+        assert s["block_size"] == nin and s["blocks"] == nin
+        # one grid line per block: lines depend on the previous line only
+        assert s["levels"] == nin and s["max_rows"] == nin
+
+
+def test_invalid_arguments_rejected():
+    with pytest.raises(pm.PmgritError) as e:
+        host_solver(1, 8)
+    assert e.value.code == -1
+    with pytest.raises(pm.PmgritError) as e:
+        host_solver(2, 8, m=1)
+    assert e.value.code == -1
+    S = host_solver(2, 6)
+    with pytest.raises(pm.PmgritError) as e:
+        S.solve_mgrit(outs=[])
+    with pytest.raises(pm.PmgritError) as e:
+        S.set_source(0, [(-1, 1, 1.0)])
+    assert e.value.code == -1
