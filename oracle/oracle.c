@@ -1049,6 +1049,12 @@ static int pmg_solve(opmg *G, const double *b, double *x) {
   int n = G->P->ndof;
   double bn = nrm2(n, b);
   G->solves++;
+  if (bn == 0.0) {
+    /* a zero right-hand side has the exact solution x = 0 (a relative stop test cannot be met
+     * from a non-zero guess) */
+    for (int i = 0; i < n; ++i) x[i] = 0.0;
+    return 0;
+  }
   for (int c = 0;; ++c) {
     residual(&G->A, b, x, G->r);
     double rn = nrm2(n, G->r);
@@ -1166,7 +1172,9 @@ typedef struct {
 } omgrit;
 
 /* one step at level l from v[k] to target k+1, written into out (which may alias v[k+1]).
- * guess policy: 0 zero, 1 previous point, 2 current value of the target. */
+ * guess policy: 0 zero, 1 previous point, 2 current value of the target at level 0 (it carries
+ * the previous MGRIT iterate) and the previous point at coarser levels (whose state restarts
+ * from zero in every cycle, so their targets carry no information in the first sweeps). */
 static void mg_step(omgrit *S, int l, int k, double *out) {
   olev *L = &S->L[l];
   int n = S->P->ndof;
@@ -1177,14 +1185,14 @@ static void mg_step(omgrit *S, int l, int k, double *out) {
     for (int i = 0; i < n; ++i) S->b[i] += c * S->F[i];
   }
   const double *tgt = L->v + (size_t)(k + 1) * n;
-  const double *gk = l > 0 ? L->g + (size_t)(k + 1) * n : NULL;
+  const double *gk = l > 0 ? L->g + (size_t)(k + 1) * n : NULL; /* coarse right-hand side, added after the solve */
   for (int i = 0; i < n; ++i) {
     if (S->guess == 0)
       S->x[i] = 0.0;
-    else if (S->guess == 1)
+    else if (S->guess == 1 || l > 0)
       S->x[i] = vk[i];
     else
-      S->x[i] = gk ? tgt[i] - gk[i] : tgt[i];
+      S->x[i] = tgt[i];
   }
   int rc = pmg_solve(&L->G, S->b, S->x);
   if (rc && !S->rc) S->rc = rc;

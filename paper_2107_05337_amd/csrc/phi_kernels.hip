@@ -252,21 +252,21 @@ __global__ void __launch_bounds__(kThreads) phi_kernel(PhiParams P, LdsPlan plan
       const double* vk = Vl + (int64_t)k * n;
       const double c = job.level == 0 ? I.scale[k + 1] : 0.0;
       spmv<8, double>(n, I.rp, I.ci, I.M, vk, 1.0, job.level == 0 ? I.F : (const double*)nullptr, c, b);
-      for (int i = threadIdx.x; i < n; i += kThreads) {
-        double v = 0.0;
-        if (P.guess == 1)
-          v = vk[i];
-        else if (P.guess == 2)
-          v = tgt[i] - (g1 ? g1[i] : 0.0);
-        x[i] = v;
-      }
+      // initial iterate: 0 zero; 1 previous point; 2 current target at level 0 (the previous
+      // MGRIT iterate), previous point at coarse levels (their state restarts from zero)
+      const bool prev = P.guess == 1 || (P.guess == 2 && job.level > 0);
+      for (int i = threadIdx.x; i < n; i += kThreads) x[i] = prev ? vk[i] : (P.guess == 2 ? tgt[i] : 0.0);
     }
     __syncthreads();
     double part = 0.0;
     for (int i = threadIdx.x; i < n; i += kThreads) part += b[i] * b[i];
     const double bn2 = block_sum(part, red);
     int cyc = 0;
-    for (;;) {
+    if (bn2 == 0.0) {  // zero right-hand side: the solution is exactly zero
+      for (int i = threadIdx.x; i < n; i += kThreads) x[i] = 0.0;
+      __syncthreads();
+    }
+    for (; bn2 != 0.0;) {
       part = residual64<8, VT>(n, I.rp, I.ci, L.A64, x, b, r);
       const double rn2 = block_sum(part, red);
       if (!(rn2 <= 1.0e300)) {  // NaN or Inf
