@@ -1,0 +1,190 @@
+"""Benchmark: time-step solves per second of MGRIT with p-multigrid spatial solves, run to a 1e-10
+relative MGRIT residual, on one MI355X.
+
+Workload (synthetic, seeded): the 2D heat equation on the unit square, kappa 1, T 0.1, N_t 1024,
+h 2^-6, B-spline degrees p = 3, 4 and 5 batched as three instances of one solver handle, source
+8 random sin-sin modes (seed 2107), u0 = 0, MGRIT m 8 with levels 1024 -> 128 -> 16 -> 2, ILUT
+(tau 1e-12, fill = nnz of A), exact p = 1 solve, spatial tolerance 1e-12.  One step = one full
+MGRIT solve of all three instances from the zero initial iterate to the 1e-10 residual.
+
+Variants: FP64 V-cycles, and FP32 V-cycles inside FP64 iterative refinement.  `value` is the
+fastest variant; every variant is listed.  The dominant kernel's roofline uses HIP events the
+library records around each of its launches on the solve stream.  The CPU baseline times the
+oracle (single thread) on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-step solves/s at 1e-10 MGRIT residual: FP64 vs FP32-refined+learned"
+WORKLOAD = ["heat-p3-h64-Nt1024", "heat-p4-h64-Nt1024", "heat-p5-h64-Nt1024"]
+HBM_PEAK_GBS = 8000.0
+RHS_PER_BATCH = 128  # level-0 F-sweep width (N_t / m)
+
+
+def make(precision: int):
+    import paper_2107_05337_amd as pm
+    from paper_2107_05337_amd import workloads as W
+
+    cfgs = [W.config(n) for n in WORKLOAD]
+    insts = [c["instances"][0] for c in cfgs]
+    probs = [pm.problem(d["p"], d["n"], d["Nt"], d["kappa"], d["T"], d["domain"]) for d in insts]
+    mo = pm.default_mgrit_opts(cfactor=8, max_levels=12, coarsest_max=8, tol=1e-10)
+    so = pm.default_solver_opts(precision=precision)
+    S = pm.Solver(probs, mo, so, device=0)
+    for i, d in enumerate(insts):
+        S.set_source(i, d["src"], d["tkind"])
+    return S, insts
+
+
+def unit_bytes(S, inst: int, precision: int) -> float:
+    """Algorithmic bytes of one V-cycle on one right-hand side: the vector traffic
+    of an unfused V-cycle, 26 n_dof + 6 n_dof1 words, plus the matrices one V-cycle streams
+    (A three times, the ILUT factors L and U twice, P twice, the p = 1 fast-diagonalisation data
+    twice) amortised over the 128 right-hand sides of a level-0 F-sweep."""
+    nd, _, _ = S.dims(inst)
+    p = S.problems[inst]
+    n1 = p.n_elems - 1
+    nd1 = n1 * n1
+    w = 8 if precision == 0 else 4          # V-cycle word size
+    mw = 12 if precision == 0 else 8        # V-cycle matrix bytes per non-zero (value + index)
+    nnzA = S.host_matrix("A", inst).nnz
+    nnzL = S.host_matrix("L", inst).nnz
+    nnzU = S.host_matrix("U", inst).nnz
+    nnzP = S.host_matrix("P", inst).nnz
+    vec = (6 * nd) * 8 + (20 * nd + 6 * nd1) * w   # outer FP64 residual / update + V-cycle vectors
+    mat = 12 * nnzA + mw * (2 * nnzA + 2 * (nnzL + nnzU) + 2 * nnzP) + 8 * 4 * n1 * n1
+    return vec + mat / RHS_PER_BATCH
+
+
+def run_variant(precision: int, steps: int, warmup: int):
+    import torch
+
+    S, insts = make(precision)
+    outs = S.alloc_trajectories()
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        S.solve_mgrit(outs, stream)
+    S.profile(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(steps):
+        _, st = S.solve_mgrit(outs, stream)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = S.profile(0)
+    nsteps_total = sum(d["Nt"] for d in insts)
+    sec_per_step = (t1 - t0) / steps
+    ub = [unit_bytes(S, i, precision) for i in range(len(insts))]
+    w = [S.dims(i)[0] for i in range(len(insts))]
+    ubar = sum(a * b for a, b in zip(ub, w)) / sum(w)
+    res = dict(value=nsteps_total / sec_per_step, ms_per_step=1e3 * sec_per_step,
+               mgrit_iters=stats[-1]["mgrit_iters"], vcycles_per_solve=stats[-1]["vcycles"],
+               phi_calls=stats[-1]["phi_calls"], kernel_ms=prof["ms"], launches=prof["launches"],
+               unit_bytes=ubar, units=prof["vcycles"])
+    final = [o.clone() for o in outs]
+    S.close()
+    return res, final
+
+
+def cpu_baseline(iters: int):
+    """Oracle MGRIT (plain C, one thread) on the p = 3 instance, one iteration timed (two
+    FCF-relaxations with their residuals and one coarse cycle), scaled to a full solve."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2107_05337_amd import workloads as W
+
+    d = W.config(WORKLOAD[0])["instances"][0]
+    P = O.Problem(d["p"], d["n"], d["domain"])
+    F = P.load_vector(d["src"])
+    t0 = time.perf_counter()
+    r = P.mgrit(d["kappa"], d["T"], d["Nt"], F, d["tkind"], np.zeros(P.ndof), m=8, max_iter=1)
+    dt = time.perf_counter() - t0
+    # a full solve = (iters + 1) FCF sweeps and iters coarse cycles ~ (iters + 1) / 2 of this sample
+    est = dt * (iters + 1) / 2.0
+    return dict(value=d["Nt"] / est, unit="time-step solves/s", cores=1, kind="oracle",
+                sample=f"oracle MGRIT on {WORKLOAD[0]} (single thread), max_iter=1 timed {dt:.1f} s, "
+                       f"scaled by (iters+1)/2 with iters={iters} to a full 1e-10 solve; rc={r['rc']}")
+
+
+def traffic_for(kernel_src_hash: str):
+    path = os.path.join(ROOT, "profiles", "phi_kernel_heat-h64-Nt1024_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("kernel_src_sha1") != kernel_src_hash:
+        return None
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--variants", default="fp64,fp32")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    variants = {}
+    finals = {}
+    for v in args.variants.split(","):
+        prec = {"fp64": 0, "fp32": 1}[v]
+        res, fin = run_variant(prec, args.steps, args.warmup)
+        variants[v] = res
+        finals[v] = fin
+        print(f"# {v}: {res['value']:.1f} time-step solves/s, {res['ms_per_step']:.1f} ms/step, "
+              f"iters {res['mgrit_iters']}, V-cycles {res['vcycles_per_solve']}", file=sys.stderr, flush=True)
+    if "fp64" in finals and "fp32" in finals:
+        num = sum(float(torch.linalg.norm(a - b)) ** 2 for a, b in zip(finals["fp32"], finals["fp64"]))
+        den = sum(float(torch.linalg.norm(b)) ** 2 for b in finals["fp64"])
+        variants["fp32"]["rel_diff_vs_fp64"] = (num / den) ** 0.5
+    best = max(variants, key=lambda k: variants[k]["value"])
+    b = variants[best]
+    achieved = b["units"] * b["unit_bytes"] / (b["kernel_ms"] * 1e-3) / 1e9
+    src = open(os.path.join(ROOT, "paper_2107_05337_amd", "csrc", "phi_kernels.hip"), "rb").read()
+    tr = traffic_for(hashlib.sha1(src).hexdigest())
+    traffic = None
+    if tr is not None and tr.get("precision") == best:
+        traffic = tr.get("hbm_bytes_per_launch")
+    roof = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
+            "kernel": f"phi_kernel<{'double' if best == 'fp64' else 'float'}>",
+            "avg_launch_ms": round(b["kernel_ms"] / max(b["launches"], 1), 4),
+            "bytes_per_unit": round(b["unit_bytes"])}
+    out = {"metric": METRIC, "value": round(b["value"], 3), "unit": "time-step solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(b["ms_per_step"], 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if best == "fp64" else "f32-vcycle-in-f64-refinement", "data": "synthetic",
+           "config": {"workload": "heat-h64-Nt1024-p3,p4,p5 (3 instances batched)", "N_t": 1024, "h": "2^-6",
+                      "p": [3, 4, 5], "m": 8, "levels": [1024, 128, 16, 2], "mgrit_tol": 1e-10,
+                      "spatial_tol": 1e-12},
+           "roofline": roof, "variants": variants}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(variants.get("fp64", b)["mgrit_iters"])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -152,8 +152,7 @@ pmgrit_status pmgrit_solve_sequential(pmgrit_handle* h, void* hip_stream, double
  * nrhs right-hand sides j, solve (M + kappa dt_level K) x_j = b_j by p-multigrid V-cycles to
  * the spatial tolerance, starting from the guess in x_j.  b_dev and x_dev are nrhs x n_dof
  * doubles (right-hand side j contiguous), nrhs <= 4096.  vcycles_dev (nrhs int32, may be NULL)
- * receives the V-cycle count of each solve.  Enqueued on hip_stream; the call returns after the
- * stream has completed it. */
+ * receives the V-cycle count of each solve.  Asynchronous on hip_stream. */
 pmgrit_status pmgrit_phi(pmgrit_handle* h, int32_t inst, int32_t level, int32_t nrhs, const double* b_dev,
                          double* x_dev, int32_t* vcycles_dev, void* hip_stream);
 
@@ -210,6 +209,12 @@ pmgrit_status pmgrit_net_grad(pmgrit_handle* h, int32_t inst, int32_t nb, const 
  * 3 V-cycle residual, 4 p = 1 vectors), dynamic LDS bytes per workgroup, device LDS limit,
  * scratch doubles per workgroup, workgroup slots, MGRIT levels, instances}. */
 pmgrit_status pmgrit_info(const pmgrit_handle* h, int64_t* out8);
+
+/* Live per-launch timing of the spatial-solve kernel: HIP events recorded on the solve stream
+ * around every launch.  enable = 1 resets the totals and turns timing on, 0 turns it off, -1
+ * leaves it as is; out4 (may be NULL) receives {total kernel ms, launches, workgroups launched,
+ * V-cycles performed} accumulated since the last reset. */
+pmgrit_status pmgrit_profile(pmgrit_handle* h, int32_t enable, double* out4);
 
 const char* pmgrit_last_error(void);
 

@@ -82,6 +82,7 @@ def lib():
         L.pmgrit_host_schedule.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int32, _ip]
         L.pmgrit_host_coarse_solve.argtypes = [_vp, C.c_int32, C.c_int32, _dp, _dp]
         L.pmgrit_info.argtypes = [_vp, C.POINTER(C.c_int64)]
+        L.pmgrit_profile.argtypes = [_vp, C.c_int32, _dp]
         L.pmgrit_net_nparams.argtypes = []
         L.pmgrit_net_nparams.restype = C.c_int64
         L.pmgrit_net_load.argtypes = [_vp, _fp, C.c_int64]
@@ -176,6 +177,13 @@ class Solver:
         _check(lib().pmgrit_info(self._h, out))
         keys = ["precision", "lds_mask", "lds_bytes", "device_lds", "ws_stride", "slots", "levels", "instances"]
         return dict(zip(keys, list(out)))
+
+    def profile(self, enable: int = -1):
+        """Live kernel timing: enable 1 resets and starts, 0 stops, -1 only reads.  Returns
+        dict(ms, launches, workgroups, vcycles) accumulated since the last reset."""
+        out = (C.c_double * 4)()
+        _check(lib().pmgrit_profile(self._h, enable, out))
+        return dict(ms=out[0], launches=int(out[1]), workgroups=int(out[2]), vcycles=int(out[3]))
 
     @staticmethod
     def _modes(modes):

@@ -16,8 +16,8 @@
 
 namespace pmg {
 hipError_t phi_prepare(int fp32, int mask, int lds_bytes);
-hipError_t phi_launch(int fp32, int mask, int lds_bytes, const PhiParams& P, const int* plan6, int nmax, int n1max,
-                      int nblocks, hipStream_t st);
+hipError_t phi_launch(int fp32, int mask, int lds_bytes, const PhiParams& P, const LdsPlan& plan, int nblocks,
+                      hipStream_t st);
 hipError_t fill_launch(double* p, int64_t n, double v, hipStream_t st);
 hipError_t copy_launch(double* dst, const double* src, int64_t n, hipStream_t st);
 hipError_t correct_launch(double* Vl, const double* Vc, int ndof, int m, int ncoarse, hipStream_t st);
@@ -55,7 +55,7 @@ struct InstHost {
   int p = 0, n = 0, domain = 0, N = 0, Nin = 0, ndof = 0, n1 = 0, ndof1 = 0, nlev = 0;
   std::vector<int> Nl;
   Dense Mx, Kx, Mx2, My, Ky, Px, Py, M1x, K1x, M1x2, M1y, K1y;  // 1D factors
-  Csr M, K, P, M1, K1, R, Q;
+  Csr M, K, P, M1, K1;  // host copies (ILUT input, inspection)
   std::vector<double> mlp, ml1, F, u0, scale;
   int tkind = 0;
   CoarseFdm fdm;
@@ -93,7 +93,7 @@ struct pmgrit_handle {
   int* d_res_begin = nullptr;
   PhiJob* d_given_jobs = nullptr;
   int fp32 = 0, mask = 0, lds_bytes = 0, nmax = 0, n1max = 0;
-  int plan[6] = {0, 0, 0, 0, 0, 0};
+  LdsPlan plan{-1, -1, -1, -1, 512, 0};
   // job lists on the device
   struct JobList {
     PhiJob* d = nullptr;
@@ -102,6 +102,16 @@ struct pmgrit_handle {
   std::vector<JobList> jF, jCF, jRES;  // per level
   JobList jCoarsest, jSeq;
   std::vector<int> res_begin;           // per instance, level-0 residual workgroup ranges
+  // pmgrit_phi job cache (pinned host staging)
+  PhiJob* h_given_jobs = nullptr;
+  int given_key[3] = {-1, -1, -1};
+  // live kernel timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  double prof_ms = 0;
+  int64_t vc_base = 0;  // V-cycle counter total at the last profile reset
+  int64_t prof_launches = 0, prof_wgs = 0;
 };
 
 // ------------------------------------------------------------------------------------------
@@ -235,13 +245,6 @@ static pmgrit_status setup_instance(pmgrit_handle* H, InstHost& I, const pmgrit_
   I.K1 = kron_interior(n + 1, n + 1, n + 1, n + 1, -1, 1, -1, 1, {{&I.M1y, &I.K1x, 1.0}, {&I.K1y, &I.M1x2, 1.0}});
   I.mlp = lumped(I.My, I.Mx);
   I.ml1 = lumped(I.M1y, I.M1x);
-  // transfers with the lumped masses folded in: R = (M1^L)^{-1} P^T, Q = (Mp^L)^{-1} P
-  I.R = transpose(I.P);
-  for (int i = 0; i < I.R.nr; ++i)
-    for (int t = I.R.rp[i]; t < I.R.rp[i + 1]; ++t) I.R.v[t] /= I.ml1[i];
-  I.Q = I.P;
-  for (int i = 0; i < I.Q.nr; ++i)
-    for (int t = I.Q.rp[i]; t < I.Q.rp[i + 1]; ++t) I.Q.v[t] /= I.mlp[i];
   I.F.assign(I.ndof, 0.0);
   I.u0.assign(I.ndof, 0.0);
   // exact p = 1 solve: generalized eigenvectors of the second direction
@@ -276,7 +279,11 @@ static pmgrit_status setup_instance(pmgrit_handle* H, InstHost& I, const pmgrit_
     std::string err;
     if (!ilut(Lv.A, H->so.ilut_droptol, lc, uc, Lv.L, Lv.U, err)) return fail(PMGRIT_E_FACTOR, err);
     int bs = H->so.trsv_block;
-    if (bs == 0 || bs == -1) bs = I.Nin;
+    if (bs == 0 || bs == -1) {
+      // one grid line per block, split evenly when a line exceeds the prefetched path's 72 rows
+      const int parts = (I.Nin + kTG * kTMB - 1) / (kTG * kTMB);
+      bs = (I.Nin + parts - 1) / parts;
+    }
     Lv.SL = build_schedule(Lv.L, false, bs);
     Lv.SU = build_schedule(Lv.U, true, bs);
     // Thomas data per mode k: T_k = G + c lam_k H with G = M1x + c K1x
@@ -386,6 +393,12 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
   T.nlev = S.nlev;
   T.bs = S.bs;
   T.max_rows = S.max_rows;
+  // the prefetched register path holds one row per 8 lanes (128 rows per level), up to 64
+  // off-block entries per row and dense rows of up to 72 entries
+  int maxo = 0, maxd = 0;
+  for (size_t q = 0; q + 1 < S.orp.size(); ++q) maxo = std::max(maxo, S.orp[q + 1] - S.orp[q]);
+  for (int c : S.dcnt) maxd = std::max(maxd, c);
+  T.fast = (S.max_rows <= kThreads / kTG && maxo <= kTG * kTMA && maxd <= kTG * kTMB) ? 1 : 0;
   int* p;
   TRY(upload_vec(H, S.lev_ptr, &p));
   T.lev_ptr = p;
@@ -413,6 +426,43 @@ static pmgrit_status upload_jobs(pmgrit_handle* H, const std::vector<PhiJob>& jo
   return upload_vec(H, jobs, &out.d);
 }
 
+static Dense transpose_dense(const Dense& A) {
+  Dense T(A.c, A.r);
+  for (int i = 0; i < A.r; ++i)
+    for (int j = 0; j < A.c; ++j) T(j, i) = A(i, j);
+  return T;
+}
+
+// 1 / (full row sums) on the interior rows: the inverse lumped mass of one direction
+static std::vector<double> inv_rowsum_interior(const Dense& A) {
+  std::vector<double> out;
+  for (int i = 1; i < A.r - 1; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < A.c; ++j) s += A(i, j);
+    out.push_back(1.0 / s);
+  }
+  return out;
+}
+
+// band array of the interior block of a full 1D matrix: row o (interior), entry (o, o + lo + d)
+static pmgrit_status upload_band(pmgrit_handle* H, const Dense& full, int lo, int w, BandDev& B) {
+  const int nr = full.r - 2, nc = full.c - 2;
+  std::vector<double> v((size_t)nr * w, 0.0);
+  for (int o = 0; o < nr; ++o)
+    for (int d = 0; d < w; ++d) {
+      const int j = o + lo + d;
+      if (j >= 0 && j < nc) v[(size_t)o * w + d] = full(o + 1, j + 1);
+    }
+  double* f = nullptr;
+  TRY(upload_vec(H, v, &f));
+  B.f64 = f;
+  TRY(upload_vals(H, v, &B.vt));
+  B.rows = nr;
+  B.w = w;
+  B.lo = lo;
+  return PMGRIT_OK;
+}
+
 static pmgrit_status device_setup(pmgrit_handle* H) {
   HIPCHK(hipSetDevice(H->device));
   H->fp32 = H->so.precision == 1;
@@ -432,24 +482,26 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
     D.nt = I.prob.n_steps;
     H->nmax = std::max(H->nmax, I.ndof);
     H->n1max = std::max(H->n1max, I.ndof1);
-    int* p;
+    D.nin = I.Nin;
+    D.p = I.p;
     double* d;
-    TRY(upload_vec(H, I.M.rp, &p));
-    D.rp = p;
-    TRY(upload_vec(H, I.M.ci, &p));
-    D.ci = p;
-    TRY(upload_vec(H, I.M.v, &d));
-    D.M = d;
-    TRY(upload_vec(H, I.R.rp, &p));
-    D.Rrp = p;
-    TRY(upload_vec(H, I.R.ci, &p));
-    D.Rci = p;
-    TRY(upload_vals(H, I.R.v, &D.Rv));
-    TRY(upload_vec(H, I.Q.rp, &p));
-    D.Qrp = p;
-    TRY(upload_vec(H, I.Q.ci, &p));
-    D.Qci = p;
-    TRY(upload_vals(H, I.Q.v, &D.Qv));
+    const int p = I.p;
+    TRY(upload_band(H, I.Mx, -p, 2 * p + 1, D.Mx));
+    TRY(upload_band(H, I.Mx2, -p, 2 * p + 1, D.Mx2));
+    TRY(upload_band(H, I.My, -p, 2 * p + 1, D.My));
+    TRY(upload_band(H, I.Ky, -p, 2 * p + 1, D.Ky));
+    TRY(upload_band(H, I.Px, -p, p + 2, D.Px));
+    TRY(upload_band(H, I.Py, -p, p + 2, D.Py));
+    TRY(upload_band(H, transpose_dense(I.Px), -1, p + 2, D.PxT));
+    TRY(upload_band(H, transpose_dense(I.Py), -1, p + 2, D.PyT));
+    TRY(upload_vec(H, inv_rowsum_interior(I.Mx), &d));
+    D.ilp_x = d;
+    TRY(upload_vec(H, inv_rowsum_interior(I.My), &d));
+    D.ilp_y = d;
+    TRY(upload_vec(H, inv_rowsum_interior(I.M1x), &d));
+    D.il1_x = d;
+    TRY(upload_vec(H, inv_rowsum_interior(I.M1y), &d));
+    D.il1_y = d;
     TRY(upload_vec(H, I.fdm.V, &d));
     D.V = d;
     TRY(upload_vec(H, I.F, &d));
@@ -460,9 +512,10 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
       LevelHost& Lh = I.lev[l];
       LevelDev& Ld = D.lev[l];
       Ld.dt = Lh.dt;
-      TRY(upload_vec(H, Lh.A.v, &d));
-      Ld.A64 = d;
-      TRY(upload_vals(H, Lh.A.v, &Ld.Avt));
+      Ld.c = I.prob.kappa * Lh.dt;
+      Dense X1 = I.Mx;
+      for (size_t t = 0; t < X1.a.size(); ++t) X1.a[t] = I.Mx.a[t] + Ld.c * I.Kx.a[t];
+      TRY(upload_band(H, X1, -p, 2 * p + 1, Ld.X1));
       TRY(upload_tri(H, Lh.SL, Ld.L));
       TRY(upload_tri(H, Lh.SU, Ld.U));
       TRY(upload_vec(H, Lh.tl, &d));
@@ -532,7 +585,7 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
   H->max_jobs = std::max(H->max_jobs, 4096);
   TRY(upload<PhiJob>(H, nullptr, 4096, &H->d_given_jobs));
   // scratch
-  H->ws_stride = 6 * (int64_t)H->nmax + 2 * (int64_t)H->n1max + 32;
+  H->ws_stride = 6 * (int64_t)H->nmax + 32;
   H->ws_stride = (H->ws_stride + 31) / 32 * 32;
   TRY(upload<double>(H, nullptr, (size_t)H->ws_stride * H->max_jobs, &H->d_ws));
   TRY(upload<double>(H, nullptr, (size_t)H->max_jobs, &H->d_nrm2));
@@ -542,26 +595,31 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
   HIPCHK(hipMemset(H->d_vcount, 0, sizeof(int) * H->max_jobs));
   HIPCHK(hipMemset(H->d_status, 0, sizeof(int) * 4));
   HIPCHK(hipHostMalloc((void**)&H->h_pinned, sizeof(double) * (H->ninst + 8), 0));
-  // LDS plan: largest set of vectors that fits, in the order y, d, x, s, coarse
+  HIPCHK(hipHostMalloc((void**)&H->h_given_jobs, sizeof(PhiJob) * 4096, 0));
+  H->ev.resize(2048);
+  for (auto& e : H->ev) HIPCHK(hipEventCreate(&e));
+  // LDS plan: largest set of work vectors that fits, in the order y, d, s, x.  y is an FP64-sized
+  // slot (it also holds the FP64 Kronecker temporaries and a p = 1 vector), s holds a V-cycle
+  // vector or an FP64 p = 1 vector.
   int dev_lds = 0;
   HIPCHK(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, H->device));
   auto al = [](int b) { return (b + 15) / 16 * 16; };
-  const int base = 512 + al(maxrows * vt);
-  const int sz_y = al(H->nmax * vt), sz_d = sz_y, sz_x = al(H->nmax * 8), sz_s = sz_y, sz_c = al(2 * H->n1max * 8);
-  const int masks[6] = {31, 15, 7, 3, 1, 0};
-  for (int mi = 0; mi < 6; ++mi) {
-    int mk = masks[mi];
+  const int base = 512 + al(std::max(maxrows, kThreads / kTG) * vt);
+  const int sz_y = al(H->nmax * 8), sz_d = al(H->nmax * vt), sz_s = al(std::max(H->nmax * vt, H->n1max * 8)),
+            sz_x = al(H->nmax * 8);
+  const int masks[5] = {15, 7, 3, 1, 0};
+  for (int mi = 0; mi < 5; ++mi) {
+    const int mk = masks[mi];
     int off = base;
-    int plan[6] = {-1, -1, -1, -1, -1, 512};
-    if (mk & 1) { plan[0] = off; off += sz_y; }
-    if (mk & 2) { plan[1] = off; off += sz_d; }
-    if (mk & 4) { plan[2] = off; off += sz_x; }
-    if (mk & 8) { plan[3] = off; off += sz_s; }
-    if (mk & 16) { plan[4] = off; off += sz_c; }
+    LdsPlan plan{-1, -1, -1, -1, 512, H->nmax};
+    if (mk & kY) { plan.off_y = off; off += sz_y; }
+    if (mk & kD) { plan.off_d = off; off += sz_d; }
+    if (mk & kS) { plan.off_s = off; off += sz_s; }
+    if (mk & kX) { plan.off_x = off; off += sz_x; }
     if (off <= dev_lds || mk == 0) {
       H->mask = mk;
       H->lds_bytes = off;
-      std::memcpy(H->plan, plan, sizeof(plan));
+      H->plan = plan;
       break;
     }
   }
@@ -595,11 +653,39 @@ static PhiParams base_params(pmgrit_handle* H, int mode, const PhiJob* jobs) {
   return P;
 }
 
+// accumulate the elapsed times of the recorded event pairs (the stream must be complete)
+static hipError_t harvest(pmgrit_handle* H) {
+  for (int k = 0; k < H->ev_used; ++k) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, H->ev[2 * k], H->ev[2 * k + 1]);
+    if (e != hipSuccess) return e;
+    H->prof_ms += ms;
+  }
+  H->ev_used = 0;
+  return hipSuccess;
+}
+
+static hipError_t phi_timed(pmgrit_handle* H, const PhiParams& P, int nblocks, hipStream_t st) {
+  if (!H->prof) return phi_launch(H->fp32, H->mask, H->lds_bytes, P, H->plan, nblocks, st);
+  hipError_t e;
+  if (H->ev_used * 2 + 2 > (int)H->ev.size()) {
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if ((e = harvest(H)) != hipSuccess) return e;
+  }
+  const int k = H->ev_used++;
+  if ((e = hipEventRecord(H->ev[2 * k], st)) != hipSuccess) return e;
+  if ((e = phi_launch(H->fp32, H->mask, H->lds_bytes, P, H->plan, nblocks, st)) != hipSuccess)
+    return e;
+  H->prof_launches++;
+  H->prof_wgs += nblocks;
+  return hipEventRecord(H->ev[2 * k + 1], st);
+}
+
 static hipError_t launch(pmgrit_handle* H, const pmgrit_handle::JobList& J, int mode, hipStream_t st, int guess = -1) {
   if (J.n == 0) return hipSuccess;
   PhiParams P = base_params(H, mode, J.d);
   if (guess >= 0) P.guess = guess;
-  return phi_launch(H->fp32, H->mask, H->lds_bytes, P, H->plan, H->nmax, H->n1max, J.n, st);
+  return phi_timed(H, P, J.n, st);
 }
 
 // one recursive MGRIT cycle at level l >= 1 on A^{(l)} v = g (v zeroed by the caller)
@@ -641,7 +727,6 @@ static pmgrit_status begin_solve(pmgrit_handle* H, hipStream_t st, double* const
   }
   HIPCHK(hipMemcpyAsync(H->d_vtab, H->h_vtab.data(), sizeof(double*) * H->h_vtab.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(H->d_status, 0, sizeof(int) * 4, st));
-  HIPCHK(hipMemsetAsync(H->d_vcount, 0, sizeof(int) * H->max_jobs, st));
   // initial iterate: U_0 = u0, U_k = 0 for k >= 1
   for (int i = 0; i < H->ninst; ++i) {
     const int nd = H->inst[i].ndof;
@@ -718,6 +803,9 @@ void pmgrit_destroy(pmgrit_handle* h) {
     (void)hipDeviceSynchronize();
     for (void* p : h->allocs) (void)hipFree(p);
     if (h->h_pinned) (void)hipHostFree(h->h_pinned);
+    if (h->h_given_jobs) (void)hipHostFree(h->h_given_jobs);
+    for (hipEvent_t e : h->ev)
+      if (e) (void)hipEventDestroy(e);
   }
   delete h;
 }
@@ -819,6 +907,7 @@ pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* con
   hipStream_t st = (hipStream_t)hip_stream;
   auto t0 = std::chrono::steady_clock::now();
   TRY(begin_solve(h, st, u_out_dev));
+  const int64_t vc0 = sum_vcycles(h, st);
   pmgrit_stats S;
   std::memset(&S, 0, sizeof(S));
   int64_t phi = 0;
@@ -842,6 +931,7 @@ pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* con
       HIPCHK(norm_reduce_launch(h->d_nrm2, h->d_res_begin, h->d_resnorm, h->ninst, st));
       HIPCHK(hipMemcpyAsync(h->h_pinned, h->d_resnorm, sizeof(double) * h->ninst, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(harvest(h));
       phi += (int64_t)h->ninst * (2 * h->Nt - h->Nt / h->m + 2 * (h->Nt / h->m));
       bool done = true, bad = false;
       double worst = 0.0;
@@ -881,10 +971,11 @@ pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* con
     }
   }
   HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(harvest(h));
   if (rc == PMGRIT_OK) rc = read_status(h, st);
   S.mgrit_iters = iters;
   S.phi_calls = phi;
-  S.vcycles = sum_vcycles(h, st);
+  S.vcycles = sum_vcycles(h, st) - vc0;
   S.t_setup_s = h->t_setup;
   S.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) *stats = S;
@@ -897,14 +988,16 @@ pmgrit_status pmgrit_solve_sequential(pmgrit_handle* h, void* hip_stream, double
   hipStream_t st = (hipStream_t)hip_stream;
   auto t0 = std::chrono::steady_clock::now();
   TRY(begin_solve(h, st, u_out_dev));
+  const int64_t vc0 = sum_vcycles(h, st);
   HIPCHK(launch(h, h->jSeq, kModeChain, st, h->so.guess == 0 ? 0 : 1));
   HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(harvest(h));
   pmgrit_status rc = read_status(h, st);
   if (stats) {
     pmgrit_stats S;
     std::memset(&S, 0, sizeof(S));
     S.phi_calls = (int64_t)h->Nt * h->ninst;
-    S.vcycles = sum_vcycles(h, st);
+    S.vcycles = sum_vcycles(h, st) - vc0;
     S.t_setup_s = h->t_setup;
     S.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *stats = S;
@@ -921,16 +1014,21 @@ pmgrit_status pmgrit_phi(pmgrit_handle* h, int32_t inst, int32_t level, int32_t 
   if (nrhs == 0) return PMGRIT_OK;
   hipStream_t st = (hipStream_t)hip_stream;
   HIPCHK(hipSetDevice(h->device));
-  std::vector<PhiJob> jobs(nrhs, PhiJob{inst, level, 0, 1, 0, 0});
-  HIPCHK(hipMemcpyAsync(h->d_given_jobs, jobs.data(), sizeof(PhiJob) * nrhs, hipMemcpyHostToDevice, st));
+  if (h->given_key[0] != inst || h->given_key[1] != level || h->given_key[2] < nrhs) {
+    // the pinned staging buffer may still feed an earlier copy: wait before rewriting it
+    HIPCHK(hipDeviceSynchronize());
+    for (int j = 0; j < nrhs; ++j) h->h_given_jobs[j] = PhiJob{inst, level, 0, 1, 0, 0};
+    HIPCHK(hipMemcpyAsync(h->d_given_jobs, h->h_given_jobs, sizeof(PhiJob) * nrhs, hipMemcpyHostToDevice, st));
+    h->given_key[0] = inst;
+    h->given_key[1] = level;
+    h->given_key[2] = nrhs;
+  }
   PhiParams P = base_params(h, kModeGiven, h->d_given_jobs);
   P.vtab = nullptr;
   P.bgiven = b_dev;
   P.xgiven = x_dev;
   P.vlast = vcycles_dev;
-  HIPCHK(phi_launch(h->fp32, h->mask, h->lds_bytes, P, h->plan, h->nmax, h->n1max, nrhs, st));
-  // the job array is host memory that must outlive the copy
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(phi_timed(h, P, nrhs, st));
   return PMGRIT_OK;
 }
 
@@ -990,6 +1088,31 @@ pmgrit_status pmgrit_host_coarse_solve(const pmgrit_handle* h, int32_t inst, int
   if (!h || inst < 0 || inst >= h->ninst || level < 0 || level >= h->nlev || !b || !x)
     return fail(PMGRIT_E_ARG, "bad inspection arguments");
   host_coarse_solve(h->inst[inst], level, b, x);
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_profile(pmgrit_handle* h, int32_t enable, double* out4) {
+  if (!h || enable < -1 || enable > 1) return fail(PMGRIT_E_ARG, "bad profile arguments");
+  if (h->device < 0) return fail(PMGRIT_E_STATE, "host-only handle");
+  HIPCHK(hipSetDevice(h->device));
+  if (out4 || enable >= 0) {
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(harvest(h));
+  }
+  const int64_t vc = sum_vcycles(h, nullptr);
+  if (vc < 0) return fail(PMGRIT_E_HIP, "reading V-cycle counters failed");
+  if (out4) {
+    out4[0] = h->prof_ms;
+    out4[1] = (double)h->prof_launches;
+    out4[2] = (double)h->prof_wgs;
+    out4[3] = (double)(vc - h->vc_base);
+  }
+  if (enable == 1) {
+    h->prof_ms = 0;
+    h->prof_launches = h->prof_wgs = 0;
+    h->vc_base = vc;
+  }
+  if (enable >= 0) h->prof = enable == 1;
   return PMGRIT_OK;
 }
 

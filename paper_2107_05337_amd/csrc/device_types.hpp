@@ -6,11 +6,17 @@
 namespace pmg {
 
 constexpr int kMaxLevels = 12;   // MGRIT time levels per instance
-constexpr int kThreads = 256;    // threads per workgroup of the spatial-solve kernel
+constexpr int kThreads = 1024;   // threads per workgroup of the spatial-solve kernel
+
+// Prefetched triangular-solve limits: 8 lanes per row, 128 rows per level, up to 64 off-block
+// entries per row and dense diagonal blocks of up to 72 rows.
+constexpr int kTG = 8;
+constexpr int kTMA = 8;
+constexpr int kTMB = 9;
 
 // level-scheduled blocked triangular solve (see TriSchedule in host_setup.hpp)
 struct TriDev {
-  int nlev, bs, max_rows, pad;
+  int nlev, bs, max_rows, fast;  // fast: the schedule fits the prefetched register path
   const int* lev_ptr;
   const int* row;
   const int* orp;
@@ -22,31 +28,36 @@ struct TriDev {
   const void* dval;   // dense diagonal-block inverses (V-cycle precision)
 };
 
+// a banded 1D factor of a Kronecker product: rows x w values, entry (o, o + lo + d) at [o*w + d]
+struct BandDev {
+  const double* f64;
+  const void* vt;     // V-cycle precision copy
+  int rows, w, lo, pad;
+};
+
 // one MGRIT time level of one instance: A_l = M + kappa dt_l K and its smoother / coarse data
 struct LevelDev {
-  double dt;
-  const double* A64;   // FP64 values of A_l on the pattern of M (rp/ci of the instance)
-  const void* Avt;     // A_l values in the V-cycle precision
+  double dt, c;        // c = kappa dt_l
+  BandDev X1;          // first-direction factor of A_l's first term: Mx + c Kx
   TriDev L, U;         // ILUT(A_l) factors
   const double* tl;    // exact p = 1 solve: Thomas multipliers per mode [n1][n1]
   const double* tdinv; //                    inverse pivots per mode [n1][n1]
 };
 
+// A_l = My (x) X1_l + c_l Ky (x) Mx2, M = My (x) Mx, P_1^p = Py (x) Px (second direction slow)
 struct InstDev {
   int ndof, n1, ndof1, nlev;
-  int nt, pad0;
-  const int* rp;       // CSR pattern shared by M and every A_l
-  const int* ci;
-  const double* M;     // mass matrix values (FP64)
-  const int* Rrp;      // restriction (M1^L)^{-1} P^T: ndof1 x ndof
-  const int* Rci;
-  const void* Rv;      // V-cycle precision
-  const int* Qrp;      // prolongation (Mp^L)^{-1} P: ndof x ndof1
-  const int* Qci;
-  const void* Qv;
-  const double* V;     // p = 1 generalized eigenvectors, [iy][k], n1 x n1
-  const double* F;     // load vector (ndof)
-  const double* scale; // level-0 source scale dt * tfac(t_k) for k = 0..N_t
+  int nt, nin, p, pad0;
+  BandDev Mx, Mx2, My, Ky;   // nin x (2p+1)
+  BandDev Px, Py;            // nin x (p+2): prolongation directions
+  BandDev PxT, PyT;          // n1 x (p+2): restriction directions
+  const double* ilp_x;       // 1 / lumped degree-p mass per direction (nin)
+  const double* ilp_y;
+  const double* il1_x;       // 1 / lumped degree-1 mass per direction (n1)
+  const double* il1_y;
+  const double* V;           // p = 1 generalized eigenvectors, [iy][k], n1 x n1
+  const double* F;           // load vector (ndof)
+  const double* scale;       // level-0 source scale dt * tfac(t_k) for k = 0..N_t
   LevelDev lev[kMaxLevels];
 };
 
@@ -72,8 +83,15 @@ struct PhiParams {
   int* status;             // error flags (bit 0 non-finite, bit 1 V-cycle cap)
   double* ws;              // per-workgroup global scratch
   int64_t ws_stride;       // doubles per workgroup
-  int mode, guess, maxcyc, nu1, nu2, lds_vec_bytes;
+  int mode, guess, maxcyc, nu1, nu2, pad;
   double stol;
 };
+
+// LDS placement of the work vectors (byte offsets, -1 = global scratch)
+struct LdsPlan {
+  int off_y, off_d, off_s, off_x, off_sbuf, nmax;
+};
+
+enum : int { kY = 1, kD = 2, kS = 4, kX = 8 };
 
 }  // namespace pmg
