@@ -92,8 +92,8 @@ struct pmgrit_handle {
   double* h_pinned = nullptr;  // resnorm copy + status
   int* d_res_begin = nullptr;
   PhiJob* d_given_jobs = nullptr;
-  int fp32 = 0, mask = 0, lds_bytes = 0, nmax = 0, n1max = 0;
-  LdsPlan plan{-1, -1, -1, -1, 512, 0};
+  int fp32 = 0, mask = 0, lds_bytes = 0, nmax = 0, n1max = 0, ka = 2, rw = 8;
+  LdsPlan plan{-1, -1, -1, -1, 512, 0, 0, 0};
   // job lists on the device
   struct JobList {
     PhiJob* d = nullptr;
@@ -281,7 +281,7 @@ static pmgrit_status setup_instance(pmgrit_handle* H, InstHost& I, const pmgrit_
     int bs = H->so.trsv_block;
     if (bs == 0 || bs == -1) {
       // one grid line per block, split evenly when a line exceeds the prefetched path's 72 rows
-      const int parts = (I.Nin + kTG * kTMB - 1) / (kTG * kTMB);
+      const int parts = (I.Nin + kDenseMax - 1) / kDenseMax;
       bs = (I.Nin + parts - 1) / parts;
     }
     Lv.SL = build_schedule(Lv.L, false, bs);
@@ -389,7 +389,7 @@ static pmgrit_status upload_vals(pmgrit_handle* H, const std::vector<double>& v,
     if (s_ != PMGRIT_OK) return s_; \
   } while (0)
 
-static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& T) {
+static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& T, int zidx, int RW) {
   T.nlev = S.nlev;
   T.bs = S.bs;
   T.max_rows = S.max_rows;
@@ -398,7 +398,11 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
   int maxo = 0, maxd = 0;
   for (size_t q = 0; q + 1 < S.orp.size(); ++q) maxo = std::max(maxo, S.orp[q + 1] - S.orp[q]);
   for (int c : S.dcnt) maxd = std::max(maxd, c);
-  T.fast = (S.max_rows <= kThreads / kTG && maxo <= kTG * kTMA && maxd <= kTG * kTMB) ? 1 : 0;
+  const size_t aslots = ((size_t)S.nlev * std::max(1, S.max_rows) + 1) * (size_t)RW;
+  T.fast = (zidx >= 0 && S.max_rows <= kRowSlots && maxo <= RW && maxo <= kOffMax && maxd <= kDenseMax &&
+            S.dval.size() + 1 < (size_t)INT32_MAX && aslots < (size_t)INT32_MAX)
+               ? 1
+               : 0;
   int* p;
   TRY(upload_vec(H, S.lev_ptr, &p));
   T.lev_ptr = p;
@@ -413,10 +417,47 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
   T.dq0 = p;
   TRY(upload_vec(H, S.dcnt, &p));
   T.dcnt = p;
+  // dense values with a reserved zero at index 0 (offsets shifted by one)
+  std::vector<double> dval(S.dval.size() + 1, 0.0);
+  std::copy(S.dval.begin(), S.dval.end(), dval.begin() + 1);
+  std::vector<int64_t> doff(S.doff.size());
+  for (size_t q = 0; q < S.doff.size(); ++q) doff[q] = S.doff[q] + 1;
   int64_t* p64;
-  TRY(upload_vec(H, S.doff, &p64));
+  TRY(upload_vec(H, doff, &p64));
   T.doff = p64;
-  TRY(upload_vals(H, S.dval, &T.dval));
+  TRY(upload_vals(H, dval, &T.dval));
+  if (T.fast) {
+    // slot tables: entry 0 reserved (empty slot / zero coefficient whose column is the LDS
+    // zero word); level l, row slot r at 1 + l * R + r; off-block entries padded to AS per row
+    const int R = std::max(1, S.max_rows), AS = RW;
+    const size_t nslots = (size_t)(S.nlev + 2) * R + 1;
+    std::vector<Meta4> meta(nslots, Meta4{-1, 0, 0, 0});
+    std::vector<int> boff(nslots, 0), acol(aslots, zidx);
+    std::vector<double> aval(aslots, 0.0);
+    for (int l = 0; l < S.nlev; ++l)
+      for (int q = S.lev_ptr[l]; q < S.lev_ptr[l + 1]; ++q) {
+        const int r = q - S.lev_ptr[l];
+        const size_t sl = (size_t)l * R + r;
+        const int na = S.orp[q + 1] - S.orp[q];
+        meta[1 + sl] = Meta4{S.row[q], na, S.dq0[q], S.dcnt[q]};
+        boff[1 + sl] = (int)(S.doff[q] + 1);
+        for (int t = 0; t < na; ++t) {
+          aval[(1 + sl) * AS + t] = S.ov[S.orp[q] + t];
+          acol[(1 + sl) * AS + t] = S.oci[S.orp[q] + t];
+        }
+      }
+    T.R = R;
+    T.AS = AS;
+    Meta4* m4;
+    TRY(upload_vec(H, meta, &m4));
+    T.meta = m4;
+    int* pi;
+    TRY(upload_vec(H, boff, &pi));
+    T.boff = pi;
+    TRY(upload_vec(H, acol, &pi));
+    T.acol = pi;
+    TRY(upload_vals(H, aval, &T.aval));
+  }
   return PMGRIT_OK;
 }
 
@@ -470,6 +511,27 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
   H->h_instdev.resize(H->ninst);
   H->nmax = 0;
   H->n1max = 0;
+  for (int i = 0; i < H->ninst; ++i) {
+    H->nmax = std::max(H->nmax, H->inst[i].ndof);
+    H->n1max = std::max(H->n1max, H->inst[i].ndof1);
+  }
+  // the y slot holds nmax doubles plus a zero word at its end (index in V-cycle words)
+  const int zidx = H->nmax * 8 / vt;
+  // off-block entries per lane of the prefetched triangular solves: the widest ILUT row of any
+  // instance, level and factor, over the 4 lanes per row, rounded up to
+  // a power of two
+  {
+    const int tg = 4;
+    int maxo = 1;
+    for (const InstHost& I : H->inst)
+      for (const LevelHost& Lh : I.lev)
+        for (const TriSchedule* S : {&Lh.SL, &Lh.SU})
+          for (size_t q = 0; q + 1 < S->orp.size(); ++q) maxo = std::max(maxo, S->orp[q + 1] - S->orp[q]);
+    int ka = 2;
+    while (ka * tg < maxo && ka < 16) ka *= 2;
+    H->ka = ka;
+    H->rw = ka * tg;
+  }
   int maxrows = 1;
   for (int i = 0; i < H->ninst; ++i) {
     InstHost& I = H->inst[i];
@@ -516,8 +578,8 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
       Dense X1 = I.Mx;
       for (size_t t = 0; t < X1.a.size(); ++t) X1.a[t] = I.Mx.a[t] + Ld.c * I.Kx.a[t];
       TRY(upload_band(H, X1, -p, 2 * p + 1, Ld.X1));
-      TRY(upload_tri(H, Lh.SL, Ld.L));
-      TRY(upload_tri(H, Lh.SU, Ld.U));
+      TRY(upload_tri(H, Lh.SL, Ld.L, zidx, H->rw));
+      TRY(upload_tri(H, Lh.SU, Ld.U, zidx, H->rw));
       TRY(upload_vec(H, Lh.tl, &d));
       Ld.tl = d;
       TRY(upload_vec(H, Lh.tdinv, &d));
@@ -604,14 +666,14 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
   int dev_lds = 0;
   HIPCHK(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, H->device));
   auto al = [](int b) { return (b + 15) / 16 * 16; };
-  const int base = 512 + al(std::max(maxrows, kThreads / kTG) * vt);
-  const int sz_y = al(H->nmax * 8), sz_d = al(H->nmax * vt), sz_s = al(std::max(H->nmax * vt, H->n1max * 8)),
+  const int base = 512 + al(std::max(maxrows, 256) * vt);  // sbuf: 256 words
+  const int sz_y = al(H->nmax * 8 + 16), sz_d = al(H->nmax * vt), sz_s = al(std::max(H->nmax * vt, H->n1max * 8)),
             sz_x = al(H->nmax * 8);
   const int masks[5] = {15, 7, 3, 1, 0};
   for (int mi = 0; mi < 5; ++mi) {
     const int mk = masks[mi];
     int off = base;
-    LdsPlan plan{-1, -1, -1, -1, 512, H->nmax};
+    LdsPlan plan{-1, -1, -1, -1, 512, H->nmax, zidx, H->ka};
     if (mk & kY) { plan.off_y = off; off += sz_y; }
     if (mk & kD) { plan.off_d = off; off += sz_d; }
     if (mk & kS) { plan.off_s = off; off += sz_s; }

@@ -6,17 +6,28 @@
 namespace pmg {
 
 constexpr int kMaxLevels = 12;   // MGRIT time levels per instance
-constexpr int kThreads = 1024;   // threads per workgroup of the spatial-solve kernel
+// Prefetched triangular-solve limits (the kernel runs 512 threads, 4 lanes per row slot): 128 row
+// slots per level, up to 64 off-block entries per row and dense diagonal blocks of up to 72 rows.
+constexpr int kRowSlots = 128;
+constexpr int kOffMax = 64;
+constexpr int kDenseMax = 72;
 
-// Prefetched triangular-solve limits: 8 lanes per row, 128 rows per level, up to 64 off-block
-// entries per row and dense diagonal blocks of up to 72 rows.
-constexpr int kTG = 8;
-constexpr int kTMA = 8;
-constexpr int kTMB = 9;
+// per (level, row slot) metadata of the prefetched triangular solve
+struct Meta4 {
+  int row, na, bq0, bcnt;  // row (or -1), off-block count, s position of the dense row, dense count
+};
 
 // level-scheduled blocked triangular solve (see TriSchedule in host_setup.hpp)
 struct TriDev {
   int nlev, bs, max_rows, fast;  // fast: the schedule fits the prefetched register path
+  // prefetched path: slot tables with addresses computable from (level, row slot, lane)
+  int R, AS, pad0, pad1;         // row slots per level, off-block row width (ka * lanes per row)
+  // entry 0 of every table is a reserved zero / empty slot
+  const Meta4* meta;             // [1 + (nlev + 2) * R]
+  const int* boff;               // [1 + (nlev + 2) * R] offset of the row's dense entries in dval
+  const void* aval;              // [(1 + nlev * R) * AS] off-block values, row 0 = padding
+  const int* acol;               // [(1 + nlev * R) * AS] off-block columns (padding: the zero word)
+  // general path: level-ordered CSR
   const int* lev_ptr;
   const int* row;
   const int* orp;
@@ -90,6 +101,8 @@ struct PhiParams {
 // LDS placement of the work vectors (byte offsets, -1 = global scratch)
 struct LdsPlan {
   int off_y, off_d, off_s, off_x, off_sbuf, nmax;
+  int zidx;       // index (in V-cycle words) of the always-zero word at the end of the y slot
+  int ka;         // off-block entries per lane of the prefetched triangular solves (2, 4, 8, 16)
 };
 
 enum : int { kY = 1, kD = 2, kS = 4, kX = 8 };

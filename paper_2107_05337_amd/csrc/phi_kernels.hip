@@ -20,6 +20,29 @@
 
 namespace pmg {
 
+// Global-memory pointer type.  Pointers read from descriptors in memory are otherwise generic
+// and their loads become flat loads, which also count against the LDS wait counter: every LDS
+// wait and LDS-only barrier would then wait for all prefetches in flight.
+template <class T>
+using G = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ const G<T>* gp(const T* p) {
+  return (const G<T>*)p;
+}
+
+// Launch shape per V-cycle precision: 512 threads (4 lanes per row, 128 row slots per
+// triangular-solve level), so each thread has a 256-register budget for the prefetch buffers.
+template <typename VT>
+struct Cfg;
+template <>
+struct Cfg<double> {
+  static constexpr int NT = 512, TG = 4;
+};
+template <>
+struct Cfg<float> {
+  static constexpr int NT = 512, TG = 4;
+};
+
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T v) {
 #pragma unroll
@@ -35,6 +58,7 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // sum over the workgroup, result on every thread (deterministic order)
+template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = group_sum<64>(v);
   const int w = threadIdx.x >> 6;
@@ -43,19 +67,19 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   __syncthreads();
   double s = 0.0;
 #pragma unroll
-  for (int i = 0; i < kThreads / 64; ++i) s += red[i];
+  for (int i = 0; i < NT / 64; ++i) s += red[i];
   return s;
 }
 
 template <typename T>
-__device__ __forceinline__ const T* band_ptr(const BandDev& B);
+__device__ __forceinline__ const G<T>* band_ptr(const BandDev& B);
 template <>
-__device__ __forceinline__ const double* band_ptr<double>(const BandDev& B) {
-  return B.f64;
+__device__ __forceinline__ const G<double>* band_ptr<double>(const BandDev& B) {
+  return gp(B.f64);
 }
 template <>
-__device__ __forceinline__ const float* band_ptr<float>(const BandDev& B) {
-  return (const float*)B.vt;
+__device__ __forceinline__ const G<float>* band_ptr<float>(const BandDev& B) {
+  return gp((const float*)B.vt);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -64,15 +88,15 @@ __device__ __forceinline__ const float* band_ptr<float>(const BandDev& B) {
 
 // first-direction pass: T[r][o] = sum_d B[o][d] * in[r][o + lo + d] for r < nrows, o < B.rows
 // (in has nin columns; band entries outside the input range are zero, their index is clamped)
-template <typename AT, typename IT, typename OT>
+template <int NT, typename AT, typename IT, typename OT>
 __device__ __forceinline__ void pass_x(int nrows, int nin, const BandDev& Bd, const IT* in, OT* out) {
-  const AT* __restrict__ B = band_ptr<AT>(Bd);
+  const G<AT>* __restrict__ B = band_ptr<AT>(Bd);
   const int nout = Bd.rows, w = Bd.w, lo = Bd.lo;
   const int tot = nrows * nout;
-  for (int t = threadIdx.x; t < tot; t += kThreads) {
+  for (int t = threadIdx.x; t < tot; t += NT) {
     const int r = t / nout, o = t - r * nout;
     const IT* src = in + r * nin;
-    const AT* b = B + o * w;
+    const G<AT>* b = B + o * w;
     AT s = 0;
     for (int d = 0; d < w; ++d) {
       int j = o + lo + d;
@@ -87,16 +111,16 @@ __device__ __forceinline__ void pass_x(int nrows, int nin, const BandDev& Bd, co
 //                                    + beta * z[o][c] (+ out[o][c] if acc)
 // for o < B.rows, c < ncols; T has nin rows.  sc(o,c) = scy[o] * scx[c] when scy is given.
 // Returns this thread's share of sum out^2 (used for residual norms).
-template <typename AT, typename TT, typename ZT, typename OT>
+template <int NT, typename AT, typename TT, typename ZT, typename OT>
 __device__ __forceinline__ double pass_y(int ncols, int nin, const BandDev& Bd, const TT* T, AT alpha, const ZT* z,
                                          AT beta, bool acc, const double* scy, const double* scx, OT* out) {
-  const AT* __restrict__ B = band_ptr<AT>(Bd);
+  const G<AT>* __restrict__ B = band_ptr<AT>(Bd);
   const int nout = Bd.rows, w = Bd.w, lo = Bd.lo;
   const int tot = nout * ncols;
   double part = 0.0;
-  for (int t = threadIdx.x; t < tot; t += kThreads) {
+  for (int t = threadIdx.x; t < tot; t += NT) {
     const int o = t / ncols, c = t - o * ncols;
-    const AT* b = B + o * w;
+    const G<AT>* b = B + o * w;
     AT s = 0;
     for (int d = 0; d < w; ++d) {
       int j = o + lo + d;
@@ -104,7 +128,7 @@ __device__ __forceinline__ double pass_y(int ncols, int nin, const BandDev& Bd, 
       s += b[d] * (AT)T[j * ncols + c];
     }
     AT v = alpha * s;
-    if (scy) v *= (AT)(scy[o] * scx[c]);
+    if (scy) v *= (AT)(gp(scy)[o] * gp(scx)[c]);
     if (z) v += beta * (AT)z[t];
     if (acc) v += (AT)out[t];
     out[t] = (OT)v;
@@ -115,16 +139,16 @@ __device__ __forceinline__ double pass_y(int ncols, int nin, const BandDev& Bd, 
 
 // out = beta z - A_l x with A_l = My (x) X1 + c Ky (x) Mx2 (temp: nin x nin scratch, may not
 // alias x or out).  Returns this thread's share of ||out||^2.
-template <typename AT, typename XT, typename ZT, typename OT, typename TT>
+template <int NT, typename AT, typename XT, typename ZT, typename OT, typename TT>
 __device__ double apply_A(const InstDev& I, const LevelDev& L, const XT* x, const ZT* z, OT* out, TT* tmp) {
   const int n = I.nin;
-  pass_x<AT>(n, n, L.X1, x, tmp);
+  pass_x<NT, AT>(n, n, L.X1, x, tmp);
   __syncthreads();
-  pass_y<AT>(n, n, I.My, tmp, (AT)-1, z, (AT)1, false, nullptr, nullptr, out);
+  pass_y<NT, AT>(n, n, I.My, tmp, (AT)-1, z, (AT)1, false, nullptr, nullptr, out);
   __syncthreads();
-  pass_x<AT>(n, n, I.Mx2, x, tmp);
+  pass_x<NT, AT>(n, n, I.Mx2, x, tmp);
   __syncthreads();
-  double part = pass_y<AT>(n, n, I.Ky, tmp, (AT)(-L.c), (const ZT*)nullptr, (AT)0, true, nullptr, nullptr, out);
+  double part = pass_y<NT, AT>(n, n, I.Ky, tmp, (AT)(-L.c), (const ZT*)nullptr, (AT)0, true, nullptr, nullptr, out);
   __syncthreads();
   return part;
 }
@@ -134,104 +158,126 @@ __device__ double apply_A(const InstDev& I, const LevelDev& L, const XT* x, cons
 // ---------------------------------------------------------------------------------------
 
 // Prefetched path: T y = in (T = L with unit diagonal, or U), solution written to y (which may
-// alias in).  Thread (r, g) = (row slot tid / 8, lane tid % 8).  Per level: phase A forms
-// s_r = in_i - sum_{off-block j} T_ij y_j (its entries were loaded during the previous level),
-// phase B multiplies each block's s by its dense diagonal-block inverse (loaded at the start of
-// the level, while phase A runs).  y and sbuf are in LDS, so the barriers fence LDS only.
-template <typename VT>
-__device__ void trsv_fast(const TriDev& T, const VT* in, VT* y, VT* sbuf) {
-  const VT* __restrict__ ov = (const VT*)T.ov;
-  const VT* __restrict__ dv = (const VT*)T.dval;
-  const int r = threadIdx.x / kTG, g = threadIdx.x & (kTG - 1);
-  int q0 = T.lev_ptr[0], q1 = T.lev_ptr[1];
-  int row = -1, na = 0;  // na: valid entries of this lane (padding never touches y: stale LDS
-                         // words of another type may hold NaN patterns)
-  VT av[kTMA];
-  int ac[kTMA];
-  {
-    const int q = q0 + r;
-    int k0 = 0, k1 = 0;
-    if (q < q1) {
-      row = T.row[q];
-      k0 = T.orp[q];
-      k1 = T.orp[q + 1];
+// alias in).  Thread (r, g) = (row slot tid / TG, lane tid % TG).  Per level: phase A forms
+// s_r = in_i - sum_{off-block j} T_ij y_j, phase B multiplies each block's s by its dense
+// diagonal-block inverse.  The schedule is stored as slot tables whose addresses follow from
+// (level, slot, lane): off-block rows are exactly KA * TG entries wide, padded with zero values
+// whose column is an LDS word y[zidx] that holds 0 (row 0 is all padding, for empty slots), so
+// every lane runs the same branch-free code.  Entry 0 of the metadata and dense tables is a
+// reserved empty / zero entry.  The level
+// loop is unrolled by two with ping-pong registers: the metadata of level l+2 and the data of
+// level l+1 are issued while level l computes, and no register is copied while its load is in
+// flight.  y and sbuf are LDS, the barriers fence LDS only, and the function is kept out of line
+// so its registers are allocated on their own.
+template <class T>
+using L3 = __attribute__((address_space(3))) T;
+
+template <typename VT, bool IN_GLOBAL, int KA>
+__device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* in_g, L3<VT>* y, L3<VT>* sbuf) {
+  constexpr int NT = Cfg<VT>::NT, TG = Cfg<VT>::TG, TMB = 72 / TG, RW = KA * TG;
+  const G<VT>* __restrict__ aval = gp((const VT*)Tp->aval);
+  const G<int>* __restrict__ acol = gp(Tp->acol);
+  const G<VT>* __restrict__ dv = gp((const VT*)Tp->dval);
+  const G<Meta4>* __restrict__ meta = gp(Tp->meta);
+  const G<int>* __restrict__ boff = gp(Tp->boff);
+  const int R = Tp->R, nlev = Tp->nlev;
+  const int r = threadIdx.x / TG, g = threadIdx.x & (TG - 1);
+  const bool slot = r < R;
+  // wavefronts whose row slots are all empty issue no loads (a wave-uniform branch)
+  const bool wave_live = (int)((threadIdx.x & ~63) / TG) < R;
+  auto load_meta = [&](int l, Meta4& m, int& bo) {
+    if (!wave_live) {
+      m.row = -1;
+      m.bq0 = 0;
+      m.bcnt = 0;
+      bo = 0;
+      return;
     }
-    na = k1 - k0;
+    const int idx = slot ? 1 + l * R + r : 0;
+    m.row = meta[idx].row;
+    m.bq0 = meta[idx].bq0;
+    m.bcnt = meta[idx].bcnt;
+    bo = boff[idx];
+  };
+  // off-block rows: a zero row at 0, slot (l, r) at RW + (l * R + r) * RW
+  auto load_a = [&](int l, VT* av, int* ac) {
+    if (!wave_live) {
 #pragma unroll
-    for (int j = 0; j < kTMA; ++j) {
-      const int k = k0 + g + j * kTG;
-      av[j] = k < k1 ? ov[k] : (VT)0;
-      ac[j] = k < k1 ? T.oci[k] : 0;
-    }
-  }
-  for (int l = 0; l < T.nlev; ++l) {
-    // dense row of this level's block (consumed after phase A)
-    VT bv[kTMB];
-    int bq0 = 0, bcnt = 0;
-    {
-      const int q = q0 + r;
-      int64_t off = 0;
-      if (q < q1) {
-        bq0 = T.dq0[q];
-        bcnt = T.dcnt[q];
-        off = T.doff[q];
+      for (int j = 0; j < KA; ++j) {
+        av[j] = (VT)0;
+        ac[j] = 0;
       }
+      return;
+    }
+    const int base = (slot && l < nlev) ? RW + (l * R + r) * RW + g : g;
 #pragma unroll
-      for (int j = 0; j < kTMB; ++j) {
-        const int c = g + j * kTG;
-        bv[j] = c < bcnt ? dv[off + c] : (VT)0;
-      }
+    for (int j = 0; j < KA; ++j) {
+      av[j] = aval[base + j * TG];
+      ac[j] = acol[base + j * TG];
     }
-    // prefetch the off-block entries of the next level
-    const int nq0 = q1, nq1 = l + 1 < T.nlev ? T.lev_ptr[l + 2] : q1;
-    int nrow = -1, nna = 0;
-    VT nv[kTMA];
-    int nc[kTMA];
-    {
-      const int q = nq0 + r;
-      int k0 = 0, k1 = 0;
-      if (q < nq1) {
-        nrow = T.row[q];
-        k0 = T.orp[q];
-        k1 = T.orp[q + 1];
-      }
-      nna = k1 - k0;
+  };
+  auto load_b = [&](const Meta4& m, int bo, VT* bv, VT& xin) {
+    if (!wave_live) {
 #pragma unroll
-      for (int j = 0; j < kTMA; ++j) {
-        const int k = k0 + g + j * kTG;
-        nv[j] = k < k1 ? ov[k] : (VT)0;
-        nc[j] = k < k1 ? T.oci[k] : 0;
-      }
+      for (int j = 0; j < TMB; ++j) bv[j] = (VT)0;
+      xin = (VT)0;
+      return;
     }
-    // phase A
+#pragma unroll
+    for (int j = 0; j < TMB; ++j) {
+      const int c = g + j * TG;
+      bv[j] = dv[c < m.bcnt ? bo + c : 0];
+    }
+    const int xi = m.row >= 0 ? m.row : 0;
+    if constexpr (IN_GLOBAL)
+      xin = gp(in_g)[xi];
+    else
+      xin = ((const L3<VT>*)in_g)[xi];
+  };
+  auto phase_a = [&](const VT* av, const int* ac, int row, VT xin) {
     VT s = 0;
 #pragma unroll
-    for (int j = 0; j < kTMA; ++j) {
-      const VT yv = y[ac[j]];
-      s += (g + j * kTG < na) ? av[j] * yv : (VT)0;
-    }
-    s = group_sum<kTG>(s);
-    if (g == 0 && row >= 0) sbuf[r] = in[row] - s;
-    lds_barrier();
-    // phase B
-    s = 0;
+    for (int j = 0; j < KA; ++j) s += av[j] * y[ac[j]];
+    s = group_sum<TG>(s);
+    if (g == 0 && row >= 0) sbuf[r] = xin - s;
+  };
+  // padding lanes carry zero coefficients; sbuf beyond the level's rows holds finite values
+  auto phase_b = [&](const VT* bv, int row, int bq0) {
+    VT s = 0;
 #pragma unroll
-    for (int j = 0; j < kTMB; ++j) {
-      const int c = g + j * kTG;
-      const VT sv = sbuf[bq0 + (c < bcnt ? c : 0)];
-      s += (c < bcnt) ? bv[j] * sv : (VT)0;
-    }
-    s = group_sum<kTG>(s);
+    for (int j = 0; j < TMB; ++j) s += bv[j] * sbuf[bq0 + g + j * TG];
+    s = group_sum<TG>(s);
     if (g == 0 && row >= 0) y[row] = s;
-    lds_barrier();
-    q0 = nq0;
-    q1 = nq1;
-    row = nrow;
-    na = nna;
-#pragma unroll
-    for (int j = 0; j < kTMA; ++j) {
-      av[j] = nv[j];
-      ac[j] = nc[j];
+  };
+  VT av[KA], bv0[TMB], bv1[TMB], x0, x1;
+  int ac[KA];
+  Meta4 M0, M1;
+  int b0, b1;
+  load_meta(0, M0, b0);
+  load_meta(1, M1, b1);
+  load_a(0, av, ac);
+  load_b(M0, b0, bv0, x0);
+  for (int l = 0; l < nlev; l += 2) {
+    {  // even level l
+      const int row = M0.row, bq = M0.bq0;
+      phase_a(av, ac, row, x0);
+      lds_barrier();
+      load_a(l + 1, av, ac);
+      load_b(M1, b1, bv1, x1);
+      load_meta(l + 2, M0, b0);
+      phase_b(bv0, row, bq);
+      lds_barrier();
+    }
+    if (l + 1 >= nlev) break;
+    {  // odd level l + 1
+      const int row = M1.row, bq = M1.bq0;
+      phase_a(av, ac, row, x1);
+      lds_barrier();
+      load_a(l + 2, av, ac);
+      load_b(M0, b0, bv0, x0);
+      load_meta(l + 3, M1, b1);
+      phase_b(bv1, row, bq);
+      lds_barrier();
     }
   }
 }
@@ -239,38 +285,56 @@ __device__ void trsv_fast(const TriDev& T, const VT* in, VT* y, VT* sbuf) {
 // General path (any schedule, y in LDS or global): same two phases with loops, full barriers.
 template <typename VT>
 __device__ void trsv_general(const TriDev& T, const VT* in, VT* y, VT* sbuf) {
-  constexpr int GA = 8, GB = 8;
-  const VT* __restrict__ ov = (const VT*)T.ov;
-  const VT* __restrict__ dv = (const VT*)T.dval;
+  constexpr int NT = Cfg<VT>::NT, GA = 8, GB = 8;
+  const G<VT>* __restrict__ ov = gp((const VT*)T.ov);
+  const G<VT>* __restrict__ dv = gp((const VT*)T.dval);
+  const G<int>* __restrict__ lev_ptr = gp(T.lev_ptr);
+  const G<int>* __restrict__ rowv = gp(T.row);
+  const G<int>* __restrict__ orp = gp(T.orp);
+  const G<int>* __restrict__ oci = gp(T.oci);
+  const G<int>* __restrict__ dq0 = gp(T.dq0);
+  const G<int>* __restrict__ dcnt = gp(T.dcnt);
+  const G<int64_t>* __restrict__ doff = gp(T.doff);
+  const int nlev = T.nlev;
   const int ga = threadIdx.x & (GA - 1), gb = threadIdx.x & (GB - 1);
-  for (int l = 0; l < T.nlev; ++l) {
-    const int q0 = T.lev_ptr[l], q1 = T.lev_ptr[l + 1];
-    for (int q = q0 + threadIdx.x / GA; q < q1; q += kThreads / GA) {
-      const int i = T.row[q];
+  for (int l = 0; l < nlev; ++l) {
+    const int q0 = lev_ptr[l], q1 = lev_ptr[l + 1];
+    for (int q = q0 + threadIdx.x / GA; q < q1; q += NT / GA) {
+      const int i = rowv[q];
       VT s = 0;
-      for (int k = T.orp[q] + ga; k < T.orp[q + 1]; k += GA) s += ov[k] * y[T.oci[k]];
+      for (int k = orp[q] + ga; k < orp[q + 1]; k += GA) s += ov[k] * y[oci[k]];
       s = group_sum<GA>(s);
       if (ga == 0) sbuf[q - q0] = in[i] - s;
     }
     __syncthreads();
-    for (int q = q0 + threadIdx.x / GB; q < q1; q += kThreads / GB) {
-      const int c0 = T.dq0[q], cn = T.dcnt[q];
-      const VT* __restrict__ dr = dv + T.doff[q];
+    for (int q = q0 + threadIdx.x / GB; q < q1; q += NT / GB) {
+      const int c0 = dq0[q], cn = dcnt[q];
+      const G<VT>* __restrict__ dr = dv + doff[q];
       VT s = 0;
       for (int c = gb; c < cn; c += GB) s += dr[c] * sbuf[c0 + c];
       s = group_sum<GB>(s);
-      if (gb == 0) y[T.row[q]] = s;
+      if (gb == 0) y[rowv[q]] = s;
     }
     __syncthreads();
   }
 }
 
-template <typename VT, bool YLDS>
-__device__ __forceinline__ void trsv(const TriDev& T, const VT* in, VT* y, VT* sbuf) {
-  if (YLDS && T.fast)
-    trsv_fast<VT>(T, in, y, sbuf);
-  else
+template <typename VT, bool YLDS, bool IN_GLOBAL>
+__device__ __forceinline__ void trsv(const TriDev& T, int ka, const VT* in, VT* y, VT* sbuf) {
+  if (YLDS && T.fast) {
+    L3<VT>* yl = (L3<VT>*)y;
+    L3<VT>* sl = (L3<VT>*)sbuf;
+    if (ka <= 2)
+      trsv_fast<VT, IN_GLOBAL, 2>(&T, in, yl, sl);
+    else if (ka <= 4)
+      trsv_fast<VT, IN_GLOBAL, 4>(&T, in, yl, sl);
+    else if (ka <= 8)
+      trsv_fast<VT, IN_GLOBAL, 8>(&T, in, yl, sl);
+    else
+      trsv_fast<VT, IN_GLOBAL, 16>(&T, in, yl, sl);
+  } else {
     trsv_general<VT>(T, in, y, sbuf);
+  }
   __syncthreads();
 }
 
@@ -278,10 +342,11 @@ __device__ __forceinline__ void trsv(const TriDev& T, const VT* in, VT* y, VT* s
 // exact p = 1 solve: fast diagonalisation c = V diag-solve(V^T c), one symmetric tridiagonal
 // system per mode of the second direction (Thomas, precomputed LDL^T).  c1 in / out, c2 temp.
 // ---------------------------------------------------------------------------------------
+template <int NT>
 __device__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, double* c2) {
   const int n1 = I.n1, nn = I.ndof1;
-  const double* __restrict__ V = I.V;
-  for (int o = threadIdx.x; o < nn; o += kThreads) {
+  const G<double>* __restrict__ V = gp(I.V);
+  for (int o = threadIdx.x; o < nn; o += NT) {
     const int k = o / n1, ix = o - k * n1;
     double s = 0.0;
 #pragma unroll 8
@@ -289,28 +354,55 @@ __device__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, do
     c2[o] = s;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < n1; k += kThreads) {
+  for (int k = threadIdx.x; k < n1; k += NT) {
+    // the coefficients are loaded 8 at a time so their latency is paid once per chunk, not per
+    // step of the recurrence
+    constexpr int CH = 8;
     double* rw = c2 + k * n1;
-    const double* __restrict__ tl = L.tl + k * n1;
-    const double* __restrict__ td = L.tdinv + k * n1;
-    double yp = rw[0];
-    rw[0] = yp * td[0];
-    for (int i = 1; i < n1; ++i) {
-      double yv = rw[i] - tl[i] * yp;
-      rw[i] = yv * td[i];
-      yp = yv;
+    const G<double>* __restrict__ tl = gp(L.tl) + k * n1;
+    const G<double>* __restrict__ td = gp(L.tdinv) + k * n1;
+    double yp = 0.0;
+    for (int i0 = 0; i0 < n1; i0 += CH) {
+      double a[CH], b[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int i = i0 + u < n1 ? i0 + u : n1 - 1;
+        a[u] = tl[i];
+        b[u] = td[i];
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int i = i0 + u;
+        if (i < n1) {
+          const double yv = rw[i] - (i > 0 ? a[u] * yp : 0.0);
+          rw[i] = yv * b[u];
+          yp = yv;
+        }
+      }
     }
-    double xn = rw[n1 - 1];
-    for (int i = n1 - 2; i >= 0; --i) {
-      xn = rw[i] - tl[i + 1] * xn;
-      rw[i] = xn;
+    double xn = 0.0;
+    for (int i1 = n1 - 1; i1 >= 0; i1 -= CH) {
+      double a[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int i = i1 - u + 1;  // multiplier l_{i+1} for row i = i1 - u
+        a[u] = (i >= 1 && i < n1) ? tl[i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int i = i1 - u;
+        if (i >= 0) {
+          xn = (i == n1 - 1) ? rw[i] : rw[i] - a[u] * xn;
+          rw[i] = xn;
+        }
+      }
     }
   }
   __syncthreads();
-  for (int o = threadIdx.x; o < nn; o += kThreads) {
+  for (int o = threadIdx.x; o < nn; o += NT) {
     const int iy = o / n1, ix = o - iy * n1;
     double s = 0.0;
-    const double* __restrict__ Vr = V + iy * n1;
+    const G<double>* __restrict__ Vr = V + iy * n1;
 #pragma unroll 8
     for (int k = 0; k < n1; ++k) s += Vr[k] * c2[k * n1 + ix];
     c1[o] = s;
@@ -323,48 +415,50 @@ __device__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, do
 // Buffers: y (nin^2 doubles, LDS first), s (>= max(nin^2 VT, n1^2 doubles)), d (nin^2 VT).
 template <typename VT, int MASK>
 __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, const VT* r, VT* d, VT* y, VT* s,
-                       VT* sbuf) {
+                       VT* sbuf, int ka) {
   constexpr bool YL = MASK & kY;
+  constexpr int NT = Cfg<VT>::NT;
   const int n = I.ndof;
   // step 1: pre-smoothing d = S r, then nu1 - 1 further steps d += S (r - A d)
-  trsv<VT, YL>(L.L, r, y, sbuf);
-  trsv<VT, YL>(L.U, y, y, sbuf);
-  for (int i = threadIdx.x; i < n; i += kThreads) d[i] = y[i];
+  trsv<VT, YL, true>(L.L, ka, r, y, sbuf);
+  trsv<VT, YL, !YL>(L.U, ka, y, y, sbuf);
+  for (int i = threadIdx.x; i < n; i += NT) d[i] = y[i];
   __syncthreads();
   for (int m = 1; m < nu1; ++m) {
-    apply_A<VT>(I, L, d, r, s, y);
-    trsv<VT, YL>(L.L, s, y, sbuf);
-    trsv<VT, YL>(L.U, y, y, sbuf);
-    for (int i = threadIdx.x; i < n; i += kThreads) d[i] += y[i];
+    apply_A<NT, VT>(I, L, d, r, s, y);
+    trsv<VT, YL, !(MASK & kS)>(L.L, ka, s, y, sbuf);
+    trsv<VT, YL, !YL>(L.U, ka, y, y, sbuf);
+    for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
     __syncthreads();
   }
   // step 2: residual restricted to p = 1, r1 = (M1^L)^{-1} P^T (r - A d); r1 lands in s
-  apply_A<VT>(I, L, d, r, s, y);
+  apply_A<NT, VT>(I, L, d, r, s, y);
   double* c1 = (double*)s;
   double* c2 = (double*)y;
-  pass_x<VT>(I.nin, I.nin, I.PxT, s, y);  // nin rows x n1 columns
+  pass_x<NT, VT>(I.nin, I.nin, I.PxT, s, y);  // nin rows x n1 columns
   __syncthreads();
-  pass_y<VT>(I.n1, I.nin, I.PyT, y, (VT)1, (const VT*)nullptr, (VT)0, false, I.il1_y, I.il1_x, c1);
+  pass_y<NT, VT>(I.n1, I.nin, I.PyT, y, (VT)1, (const VT*)nullptr, (VT)0, false, I.il1_y, I.il1_x, c1);
   __syncthreads();
   // step 3: exact p = 1 solve (FP64)
-  coarse_solve(I, L, c1, c2);
+  coarse_solve<NT>(I, L, c1, c2);
   // step 4: prolongation and update d += (Mp^L)^{-1} P e1
-  pass_x<VT>(I.n1, I.n1, I.Px, c1, y);  // n1 rows x nin columns
+  pass_x<NT, VT>(I.n1, I.n1, I.Px, c1, y);  // n1 rows x nin columns
   __syncthreads();
-  pass_y<VT>(I.nin, I.n1, I.Py, y, (VT)1, (const VT*)nullptr, (VT)0, true, I.ilp_y, I.ilp_x, d);
+  pass_y<NT, VT>(I.nin, I.n1, I.Py, y, (VT)1, (const VT*)nullptr, (VT)0, true, I.ilp_y, I.ilp_x, d);
   __syncthreads();
   // step 5: nu2 post-smoothing steps d += S (r - A d)
   for (int m = 0; m < nu2; ++m) {
-    apply_A<VT>(I, L, d, r, s, y);
-    trsv<VT, YL>(L.L, s, y, sbuf);
-    trsv<VT, YL>(L.U, y, y, sbuf);
-    for (int i = threadIdx.x; i < n; i += kThreads) d[i] += y[i];
+    apply_A<NT, VT>(I, L, d, r, s, y);
+    trsv<VT, YL, !(MASK & kS)>(L.L, ka, s, y, sbuf);
+    trsv<VT, YL, !YL>(L.U, ka, y, y, sbuf);
+    for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
     __syncthreads();
   }
 }
 
 template <typename VT, int MASK>
-__global__ void __launch_bounds__(kThreads) phi_kernel(PhiParams P, LdsPlan plan) {
+__global__ void __launch_bounds__(Cfg<VT>::NT) phi_kernel(PhiParams P, LdsPlan plan) {
+  constexpr int NT = Cfg<VT>::NT;
   extern __shared__ __align__(16) unsigned char smem[];
   const PhiJob job = P.jobs[blockIdx.x];
   const InstDev& I = P.inst[job.inst];
@@ -382,8 +476,14 @@ __global__ void __launch_bounds__(kThreads) phi_kernel(PhiParams P, LdsPlan plan
   VT* d = (MASK & kD) ? (VT*)(smem + plan.off_d) : (VT*)(ws + 4 * nm);
   VT* s = (MASK & kS) ? (VT*)(smem + plan.off_s) : (VT*)(ws + 5 * nm);
 
+  // the triangular solves read padding columns from the LDS word y[zidx], which stays zero, and
+  // read sbuf (256 words) beyond a level's rows with zero coefficients: make it finite once
+  if ((MASK & kY) && threadIdx.x == 0) y[plan.zidx] = (VT)0;
+  for (int i = threadIdx.x; i < 256; i += NT) sbuf[i] = (VT)0;
   double* Vl = P.vtab ? P.vtab[job.inst * kMaxLevels + job.level] : nullptr;
   const double* Gl = (P.gtab && job.level > 0) ? P.gtab[job.inst * kMaxLevels + job.level] : nullptr;
+  const double* Fv = I.F;
+  const double* scale = I.scale;
   const double stol2 = P.stol * P.stol;
   int total = 0;
   for (int st = 0; st < job.len; ++st) {
@@ -394,43 +494,43 @@ __global__ void __launch_bounds__(kThreads) phi_kernel(PhiParams P, LdsPlan plan
     if (P.mode == kModeGiven) {
       const double* bg = P.bgiven + (int64_t)blockIdx.x * n;
       const double* xg = P.xgiven + (int64_t)blockIdx.x * n;
-      for (int i = threadIdx.x; i < n; i += kThreads) {
+      for (int i = threadIdx.x; i < n; i += NT) {
         b[i] = bg[i];
         x[i] = xg[i];
       }
     } else {
       const double* vk = Vl + (int64_t)k * n;
-      const double c = job.level == 0 ? I.scale[k + 1] : 0.0;
-      pass_x<double>(I.nin, I.nin, I.Mx, vk, yd);
+      const double c = job.level == 0 ? scale[k + 1] : 0.0;
+      pass_x<NT, double>(I.nin, I.nin, I.Mx, vk, yd);
       __syncthreads();
-      pass_y<double>(I.nin, I.nin, I.My, yd, 1.0, job.level == 0 ? I.F : (const double*)nullptr, c, false,
+      pass_y<NT, double>(I.nin, I.nin, I.My, yd, 1.0, job.level == 0 ? Fv : (const double*)nullptr, c, false,
                      nullptr, nullptr, b);
       // initial iterate: 0 zero; 1 previous point; 2 current target at level 0 (the previous
       // MGRIT iterate), previous point at coarse levels (their state restarts from zero)
       const bool prev = P.guess == 1 || (P.guess == 2 && job.level > 0);
-      for (int i = threadIdx.x; i < n; i += kThreads) x[i] = prev ? vk[i] : (P.guess == 2 ? tgt[i] : 0.0);
+      for (int i = threadIdx.x; i < n; i += NT) x[i] = prev ? vk[i] : (P.guess == 2 ? tgt[i] : 0.0);
     }
     __syncthreads();
     double part = 0.0;
-    for (int i = threadIdx.x; i < n; i += kThreads) part += b[i] * b[i];
-    const double bn2 = block_sum(part, red);
+    for (int i = threadIdx.x; i < n; i += NT) part += b[i] * b[i];
+    const double bn2 = block_sum<NT>(part, red);
     int cyc = 0;
     if (bn2 == 0.0) {  // zero right-hand side: the solution is exactly zero
-      for (int i = threadIdx.x; i < n; i += kThreads) x[i] = 0.0;
+      for (int i = threadIdx.x; i < n; i += NT) x[i] = 0.0;
       __syncthreads();
     }
     for (; bn2 != 0.0;) {
       // FP64 residual r = b - A x (stored in the V-cycle precision) and its norm
       part = 0.0;
       if constexpr (sizeof(VT) == 8) {
-        part = apply_A<double>(I, L, x, b, r, yd);
+        part = apply_A<NT, double>(I, L, x, b, r, yd);
       } else {
         // residual in FP64 through the FP64 temp, then rounded into r
         double* rr = (double*)(ws + 5 * nm);  // FP64 residual staging in global scratch
-        part = apply_A<double>(I, L, x, b, rr, yd);
-        for (int i = threadIdx.x; i < n; i += kThreads) r[i] = (VT)rr[i];
+        part = apply_A<NT, double>(I, L, x, b, rr, yd);
+        for (int i = threadIdx.x; i < n; i += NT) r[i] = (VT)rr[i];
       }
-      const double rn2 = block_sum(part, red);
+      const double rn2 = block_sum<NT>(part, red);
       if (!(rn2 <= 1.0e300)) {  // NaN or Inf
         if (threadIdx.x == 0) atomicOr(P.status, 1);
         break;
@@ -440,28 +540,28 @@ __global__ void __launch_bounds__(kThreads) phi_kernel(PhiParams P, LdsPlan plan
         if (threadIdx.x == 0) atomicOr(P.status, 2);
         break;
       }
-      vcycle<VT, MASK>(I, L, P.nu1, P.nu2, r, d, y, s, sbuf);
-      for (int i = threadIdx.x; i < n; i += kThreads) x[i] += (double)d[i];
+      vcycle<VT, MASK>(I, L, P.nu1, P.nu2, r, d, y, s, sbuf, plan.ka);
+      for (int i = threadIdx.x; i < n; i += NT) x[i] += (double)d[i];
       __syncthreads();
       ++cyc;
     }
     total += cyc;
     // output
     if (P.mode == kModeChain) {
-      for (int i = threadIdx.x; i < n; i += kThreads) tgt[i] = x[i] + (g1 ? g1[i] : 0.0);
+      for (int i = threadIdx.x; i < n; i += NT) tgt[i] = x[i] + (g1 ? g1[i] : 0.0);
     } else if (P.mode == kModeResidual) {
       double* ro = P.gtab[job.inst * kMaxLevels + job.level + 1] + (int64_t)job.outj * n;
       part = 0.0;
-      for (int i = threadIdx.x; i < n; i += kThreads) {
+      for (int i = threadIdx.x; i < n; i += NT) {
         double v = x[i] + (g1 ? g1[i] : 0.0) - tgt[i];
         ro[i] = v;
         part += v * v;
       }
-      const double r2 = block_sum(part, red);
+      const double r2 = block_sum<NT>(part, red);
       if (threadIdx.x == 0) P.nrm2[blockIdx.x] = r2;
     } else {
       double* xg = P.xgiven + (int64_t)blockIdx.x * n;
-      for (int i = threadIdx.x; i < n; i += kThreads) xg[i] = x[i];
+      for (int i = threadIdx.x; i < n; i += NT) xg[i] = x[i];
     }
     __syncthreads();
   }
@@ -537,7 +637,7 @@ hipError_t phi_prepare(int fp32, int mask, int lds_bytes) {
 hipError_t phi_launch(int fp32, int mask, int lds_bytes, const PhiParams& P, const LdsPlan& plan, int nblocks,
                       hipStream_t st) {
   PhiFn f = fp32 ? pick<float>(mask) : pick<double>(mask);
-  hipLaunchKernelGGL(f, dim3(nblocks), dim3(kThreads), lds_bytes, st, P, plan);
+  hipLaunchKernelGGL(f, dim3(nblocks), dim3(fp32 ? Cfg<float>::NT : Cfg<double>::NT), lds_bytes, st, P, plan);
   return hipGetLastError();
 }
 
