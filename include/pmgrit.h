@@ -204,11 +204,20 @@ pmgrit_status pmgrit_net_train_step(pmgrit_handle* h, int32_t inst, int32_t nb, 
 pmgrit_status pmgrit_net_grad(pmgrit_handle* h, int32_t inst, int32_t nb, const float* x_dev, const float* t_dev,
                               float* grad_host, float* loss_host, void* hip_stream);
 
-/* Launch configuration chosen at create (for logs and tests): out8 = {precision,
- * lds placement mask (bit 0 triangular-solve vector, 1 V-cycle iterate, 2 FP64 iterate,
- * 3 V-cycle residual, 4 p = 1 vectors), dynamic LDS bytes per workgroup, device LDS limit,
- * scratch doubles per workgroup, workgroup slots, MGRIT levels, instances}. */
+/* Launch configuration chosen at create for the first launch group (for logs and tests):
+ * out8 = {precision, LDS placement mask (bit 0 triangular-solve vector y, 1 V-cycle correction
+ * d, 2 V-cycle residual / p = 1 vector s, 3 FP64 iterate x; a clear bit means global
+ * scratch), dynamic LDS bytes per workgroup, device LDS limit, scratch doubles per workgroup,
+ * workgroup slots, MGRIT levels, instances}.  Errors: PMGRIT_E_ARG for NULL arguments. */
 pmgrit_status pmgrit_info(const pmgrit_handle* h, int64_t* out8);
+
+/* Launch group of an instance.  Instances are grouped by the LDS placement their sizes allow;
+ * each group launches with its own configuration on its own stream, forked from and joined
+ * back into the caller's stream at every sweep.  out8 = {group id, number of groups, LDS mask,
+ * dynamic LDS bytes, off-block entries per lane of the triangular solves, instances in the
+ * group, largest dof count in the group, workgroup slots}.  Errors: PMGRIT_E_ARG for a bad
+ * instance or NULL out8, PMGRIT_E_STATE for a host-only handle. */
+pmgrit_status pmgrit_group_info(const pmgrit_handle* h, int32_t inst, int64_t* out8);
 
 /* Live per-launch timing of the spatial-solve kernel: HIP events recorded on the solve stream
  * around every launch.  enable = 1 resets the totals and turns timing on, 0 turns it off, -1

@@ -82,6 +82,7 @@ def lib():
         L.pmgrit_host_schedule.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int32, _ip]
         L.pmgrit_host_coarse_solve.argtypes = [_vp, C.c_int32, C.c_int32, _dp, _dp]
         L.pmgrit_info.argtypes = [_vp, C.POINTER(C.c_int64)]
+        L.pmgrit_group_info.argtypes = [_vp, C.c_int32, C.POINTER(C.c_int64)]
         L.pmgrit_profile.argtypes = [_vp, C.c_int32, _dp]
         L.pmgrit_net_nparams.argtypes = []
         L.pmgrit_net_nparams.restype = C.c_int64
@@ -176,6 +177,13 @@ class Solver:
         out = (C.c_int64 * 8)()
         _check(lib().pmgrit_info(self._h, out))
         keys = ["precision", "lds_mask", "lds_bytes", "device_lds", "ws_stride", "slots", "levels", "instances"]
+        return dict(zip(keys, list(out)))
+
+    def group_info(self, inst: int = 0):
+        """Launch group of instance inst: dict(group, groups, lds_mask, lds_bytes, ka, size, nmax, slots)."""
+        out = (C.c_int64 * 8)()
+        _check(lib().pmgrit_group_info(self._h, inst, out))
+        keys = ["group", "groups", "lds_mask", "lds_bytes", "ka", "size", "nmax", "slots"]
         return dict(zip(keys, list(out)))
 
     def profile(self, enable: int = -1):

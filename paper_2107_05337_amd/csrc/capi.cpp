@@ -6,8 +6,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pmgrit.h"
@@ -21,10 +24,13 @@ hipError_t phi_launch(int fp32, int mask, int lds_bytes, const PhiParams& P, con
 hipError_t fill_launch(double* p, int64_t n, double v, hipStream_t st);
 hipError_t copy_launch(double* dst, const double* src, int64_t n, hipStream_t st);
 hipError_t correct_launch(double* Vl, const double* Vc, int ndof, int m, int ncoarse, hipStream_t st);
-hipError_t norm_reduce_launch(const double* nrm2, const int* begin, double* out, int ninst, hipStream_t st);
+hipError_t norm_reduce_launch(const double* nrm2, const int* begin, const int* id, double* out, int ninst,
+                              hipStream_t st);
 }  // namespace pmg
 
 using namespace pmg;
+
+constexpr int kGivenMax = 1024;  // right-hand sides per pmgrit_phi call
 
 static thread_local std::string g_err;
 
@@ -82,29 +88,40 @@ struct pmgrit_handle {
   double** d_vtab = nullptr;
   double** d_gtab = nullptr;
   std::vector<double*> h_vtab, h_gtab;
-  double* d_ws = nullptr;
-  int64_t ws_stride = 0;
-  int max_jobs = 0;
-  double* d_nrm2 = nullptr;
-  int* d_vcount = nullptr;
   int* d_status = nullptr;
   double* d_resnorm = nullptr;
-  double* h_pinned = nullptr;  // resnorm copy + status
-  int* d_res_begin = nullptr;
-  PhiJob* d_given_jobs = nullptr;
-  int fp32 = 0, mask = 0, lds_bytes = 0, nmax = 0, n1max = 0, ka = 2, rw = 8;
-  LdsPlan plan{-1, -1, -1, -1, 512, 0, 0, 0};
-  // job lists on the device
+  double* h_pinned = nullptr;  // residual norms read back per MGRIT iteration
+  PhiJob* h_given_jobs = nullptr;
+  int given_key[3] = {-1, -1, -1};
+  int fp32 = 0;
   struct JobList {
     PhiJob* d = nullptr;
     int n = 0;
+    int64_t steps = 0;  // spatial solves the list performs
   };
-  std::vector<JobList> jF, jCF, jRES;  // per level
-  JobList jCoarsest, jSeq;
-  std::vector<int> res_begin;           // per instance, level-0 residual workgroup ranges
-  // pmgrit_phi job cache (pinned host staging)
-  PhiJob* h_given_jobs = nullptr;
-  int given_key[3] = {-1, -1, -1};
+  // Instances are grouped by the LDS placement they can use; every group has its own launch
+  // configuration, job lists and scratch, and launches on its own stream so that groups of
+  // different sizes run concurrently within a sweep.
+  struct Group {
+    std::vector<int> inst;
+    int mask = 0, lds_bytes = 0, nmax = 0, n1max = 0, ka = 2, rw = 8, maxrows = 1;
+    LdsPlan plan{-1, -1, -1, -1, 512, 0, 0, 2};
+    std::vector<JobList> jF, jCF, jRES;
+    JobList jCoarsest, jSeq;
+    int max_jobs = 0;
+    double* d_ws = nullptr;
+    int64_t ws_stride = 0;
+    double* d_nrm2 = nullptr;
+    int* d_vcount = nullptr;
+    int* d_res_begin = nullptr;  // level-0 residual workgroup ranges per group-local instance
+    int* d_res_inst = nullptr;   // their global instance ids
+    PhiJob* d_given_jobs = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+  };
+  std::vector<Group> groups;
+  std::vector<int> inst_group;
+  hipEvent_t fork = nullptr;
   // live kernel timing
   bool prof = false;
   std::vector<hipEvent_t> ev;
@@ -251,64 +268,103 @@ static pmgrit_status setup_instance(pmgrit_handle* H, InstHost& I, const pmgrit_
   {
     Dense My1 = interior(I.M1y), Ky1 = interior(I.K1y);
     Dense V;
-    if (!gen_eig(Ky1, My1, I.fdm.lam, V)) return fail(PMGRIT_E_FACTOR, "p=1 mass matrix not SPD");
+    if (!gen_eig(Ky1, My1, I.fdm.lam, V)) return PMGRIT_E_FACTOR;
     I.fdm.n1 = I.n1;
     I.fdm.V = V.a;
   }
-  // time levels
+  // time levels (factored by setup_level, in parallel over instances and levels)
   const double dt0 = pr.T / pr.n_steps;
   I.nlev = H->nlev;
   I.lev.resize(I.nlev);
-  Dense G1 = interior(I.M1x), K1i = interior(I.K1x), H1 = interior(I.M1x2);
-  for (int l = 0; l < I.nlev; ++l) {
-    LevelHost& Lv = I.lev[l];
-    Lv.dt = dt0 * std::pow((double)H->m, l);
-    const double c = pr.kappa * Lv.dt;
-    Lv.A = I.M;
-    for (size_t t = 0; t < Lv.A.v.size(); ++t) Lv.A.v[t] = I.M.v[t] + c * I.K.v[t];
-    std::vector<int> lc(I.ndof), uc(I.ndof);
-    for (int i = 0; i < I.ndof; ++i) {
-      int lo = 0, up = 0;
-      for (int t = Lv.A.rp[i]; t < Lv.A.rp[i + 1]; ++t) {
-        lo += Lv.A.ci[t] < i;
-        up += Lv.A.ci[t] > i;
-      }
-      lc[i] = lo;
-      uc[i] = up;
-    }
-    std::string err;
-    if (!ilut(Lv.A, H->so.ilut_droptol, lc, uc, Lv.L, Lv.U, err)) return fail(PMGRIT_E_FACTOR, err);
-    int bs = H->so.trsv_block;
-    if (bs == 0 || bs == -1) {
-      // one grid line per block, split evenly when a line exceeds the prefetched path's 72 rows
-      const int parts = (I.Nin + kDenseMax - 1) / kDenseMax;
-      bs = (I.Nin + parts - 1) / parts;
-    }
-    Lv.SL = build_schedule(Lv.L, false, bs);
-    Lv.SU = build_schedule(Lv.U, true, bs);
-    // Thomas data per mode k: T_k = G + c lam_k H with G = M1x + c K1x
-    const int n1 = I.n1;
-    Lv.tl.assign((size_t)n1 * n1, 0.0);
-    Lv.tdinv.assign((size_t)n1 * n1, 0.0);
-    for (int k = 0; k < n1; ++k) {
-      double dprev = 0.0;
-      for (int i = 0; i < n1; ++i) {
-        double diag = G1(i, i) + c * K1i(i, i) + c * I.fdm.lam[k] * H1(i, i);
-        double li = 0.0;
-        if (i > 0) {
-          double off = G1(i, i - 1) + c * K1i(i, i - 1) + c * I.fdm.lam[k] * H1(i, i - 1);
-          li = off / dprev;
-          diag -= li * off;
-        }
-        if (!(diag > 0)) return fail(PMGRIT_E_FACTOR, "p=1 tridiagonal not SPD");
-        Lv.tl[(size_t)k * n1 + i] = li;
-        Lv.tdinv[(size_t)k * n1 + i] = 1.0 / diag;
-        dprev = diag;
-      }
-    }
-  }
   I.scale.assign(pr.n_steps + 1, dt0);
   return PMGRIT_OK;
+}
+
+// One time level of one instance: A_l = M + kappa dt_l K, ILUT(A_l), the blocked triangular
+// schedules of its factors and the Thomas data of the exact p = 1 solve.  Runs on a worker
+// thread: reports failures through err instead of the thread-local error message.
+static pmgrit_status setup_level(const pmgrit_handle* H, InstHost& I, int l, std::string& err) {
+  const pmgrit_problem& pr = I.prob;
+  const double dt0 = pr.T / pr.n_steps;
+  Dense G1 = interior(I.M1x), K1i = interior(I.K1x), H1 = interior(I.M1x2);
+  LevelHost& Lv = I.lev[l];
+  Lv.dt = dt0 * std::pow((double)H->m, l);
+  const double c = pr.kappa * Lv.dt;
+  Lv.A = I.M;
+  for (size_t t = 0; t < Lv.A.v.size(); ++t) Lv.A.v[t] = I.M.v[t] + c * I.K.v[t];
+  std::vector<int> lc(I.ndof), uc(I.ndof);
+  for (int i = 0; i < I.ndof; ++i) {
+    int lo = 0, up = 0;
+    for (int t = Lv.A.rp[i]; t < Lv.A.rp[i + 1]; ++t) {
+      lo += Lv.A.ci[t] < i;
+      up += Lv.A.ci[t] > i;
+    }
+    lc[i] = lo;
+    uc[i] = up;
+  }
+  if (!ilut(Lv.A, H->so.ilut_droptol, lc, uc, Lv.L, Lv.U, err)) return PMGRIT_E_FACTOR;
+  int bs = H->so.trsv_block;
+  if (bs == 0 || bs == -1) {
+    // one grid line per block, split evenly when a line exceeds the prefetched path's 72 rows
+    const int parts = (I.Nin + kDenseMax - 1) / kDenseMax;
+    bs = (I.Nin + parts - 1) / parts;
+  }
+  Lv.SL = build_schedule(Lv.L, false, bs);
+  Lv.SU = build_schedule(Lv.U, true, bs);
+  // Thomas data per mode k: T_k = G + c lam_k H with G = M1x + c K1x
+  const int n1 = I.n1;
+  Lv.tl.assign((size_t)n1 * n1, 0.0);
+  Lv.tdinv.assign((size_t)n1 * n1, 0.0);
+  for (int k = 0; k < n1; ++k) {
+    double dprev = 0.0;
+    for (int i = 0; i < n1; ++i) {
+      double diag = G1(i, i) + c * K1i(i, i) + c * I.fdm.lam[k] * H1(i, i);
+      double li = 0.0;
+      if (i > 0) {
+        double off = G1(i, i - 1) + c * K1i(i, i - 1) + c * I.fdm.lam[k] * H1(i, i - 1);
+        li = off / dprev;
+        diag -= li * off;
+      }
+      if (!(diag > 0)) {
+        err = "p=1 tridiagonal not SPD";
+        return PMGRIT_E_FACTOR;
+      }
+      Lv.tl[(size_t)k * n1 + i] = li;
+      Lv.tdinv[(size_t)k * n1 + i] = 1.0 / diag;
+      dprev = diag;
+    }
+  }
+  return PMGRIT_OK;
+}
+
+// run f(t) for t in [0, ntask) on up to 16 host threads; returns the first failure
+template <class F>
+static pmgrit_status parallel_tasks(int ntask, F f, std::string& err) {
+  std::atomic<int> next{0};
+  std::mutex mu;
+  pmgrit_status first = PMGRIT_OK;
+  auto worker = [&]() {
+    for (;;) {
+      const int t = next.fetch_add(1);
+      if (t >= ntask) return;
+      std::string e;
+      const pmgrit_status s = f(t, e);
+      if (s != PMGRIT_OK) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (first == PMGRIT_OK) {
+          first = s;
+          err = e;
+        }
+      }
+    }
+  };
+  int nth = (int)std::thread::hardware_concurrency();
+  nth = std::max(1, std::min({nth, 16, ntask}));
+  std::vector<std::thread> pool;
+  for (int i = 1; i < nth; ++i) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
+  return first;
 }
 
 // host version of the exact p = 1 solve (for testing the setup)
@@ -461,9 +517,12 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
   return PMGRIT_OK;
 }
 
-static pmgrit_status upload_jobs(pmgrit_handle* H, const std::vector<PhiJob>& jobs, pmgrit_handle::JobList& out) {
+static pmgrit_status upload_jobs(pmgrit_handle* H, pmgrit_handle::Group& G, const std::vector<PhiJob>& jobs,
+                                 pmgrit_handle::JobList& out) {
   out.n = (int)jobs.size();
-  H->max_jobs = std::max(H->max_jobs, out.n);
+  out.steps = 0;
+  for (const PhiJob& j : jobs) out.steps += j.len;
+  G.max_jobs = std::max(G.max_jobs, out.n);
   return upload_vec(H, jobs, &out.d);
 }
 
@@ -504,46 +563,95 @@ static pmgrit_status upload_band(pmgrit_handle* H, const Dense& full, int lo, in
   return PMGRIT_OK;
 }
 
+// LDS plan for a launch configuration: the largest set of work vectors that fits, in the order
+// y, d, s, x.  y is an FP64-sized slot plus a zero word (it also holds the FP64 Kronecker
+// temporaries and a p = 1 vector), s holds a V-cycle vector or an FP64 p = 1 vector.
+static void lds_plan(int nmax, int n1max, int maxrows, int vt, int ka, int dev_lds, int& mask, int& bytes,
+                     LdsPlan& out) {
+  auto al = [](int b) { return (b + 15) / 16 * 16; };
+  const int base = 512 + al(std::max(maxrows, 256) * vt);  // block-sum scratch, sbuf (256 words)
+  const int sz_y = al(nmax * 8 + 16), sz_d = al(nmax * vt), sz_s = al(std::max(nmax * vt, n1max * 8)),
+            sz_x = al(nmax * 8);
+  const int masks[5] = {15, 7, 3, 1, 0};
+  for (int mi = 0; mi < 5; ++mi) {
+    const int mk = masks[mi];
+    int off = base;
+    LdsPlan plan{-1, -1, -1, -1, 512, nmax, nmax * 8 / vt, ka};
+    if (mk & kY) { plan.off_y = off; off += sz_y; }
+    if (mk & kD) { plan.off_d = off; off += sz_d; }
+    if (mk & kS) { plan.off_s = off; off += sz_s; }
+    if (mk & kX) { plan.off_x = off; off += sz_x; }
+    if (off <= dev_lds || mk == 0) {
+      mask = mk;
+      bytes = off;
+      out = plan;
+      return;
+    }
+  }
+}
+
+static int inst_maxrows(const InstHost& I) {
+  int r = 1;
+  for (const LevelHost& Lh : I.lev) r = std::max(r, std::max(Lh.SL.max_rows, Lh.SU.max_rows));
+  return r;
+}
+
+static int inst_max_offblock(const InstHost& I) {
+  int maxo = 1;
+  for (const LevelHost& Lh : I.lev)
+    for (const TriSchedule* S : {&Lh.SL, &Lh.SU})
+      for (size_t q = 0; q + 1 < S->orp.size(); ++q) maxo = std::max(maxo, S->orp[q + 1] - S->orp[q]);
+  return maxo;
+}
+
 static pmgrit_status device_setup(pmgrit_handle* H) {
   HIPCHK(hipSetDevice(H->device));
   H->fp32 = H->so.precision == 1;
   const int vt = H->fp32 ? 4 : 8;
-  H->h_instdev.resize(H->ninst);
-  H->nmax = 0;
-  H->n1max = 0;
-  for (int i = 0; i < H->ninst; ++i) {
-    H->nmax = std::max(H->nmax, H->inst[i].ndof);
-    H->n1max = std::max(H->n1max, H->inst[i].ndof1);
-  }
-  // the y slot holds nmax doubles plus a zero word at its end (index in V-cycle words)
-  const int zidx = H->nmax * 8 / vt;
-  // off-block entries per lane of the prefetched triangular solves: the widest ILUT row of any
-  // instance, level and factor, over the 4 lanes per row, rounded up to
-  // a power of two
+  int dev_lds = 0;
+  HIPCHK(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, H->device));
+  // group the instances by the LDS placement each would get on its own
+  H->inst_group.assign(H->ninst, -1);
   {
-    const int tg = 4;
-    int maxo = 1;
-    for (const InstHost& I : H->inst)
-      for (const LevelHost& Lh : I.lev)
-        for (const TriSchedule* S : {&Lh.SL, &Lh.SU})
-          for (size_t q = 0; q + 1 < S->orp.size(); ++q) maxo = std::max(maxo, S->orp[q + 1] - S->orp[q]);
-    int ka = 2;
-    while (ka * tg < maxo && ka < 16) ka *= 2;
-    H->ka = ka;
-    H->rw = ka * tg;
+    std::vector<int> mk(H->ninst);
+    for (int i = 0; i < H->ninst; ++i) {
+      const InstHost& I = H->inst[i];
+      int bytes;
+      LdsPlan pl;
+      lds_plan(I.ndof, I.ndof1, inst_maxrows(I), vt, 16, dev_lds, mk[i], bytes, pl);
+    }
+    for (int want : {15, 7, 3, 1, 0}) {
+      pmgrit_handle::Group G;
+      for (int i = 0; i < H->ninst; ++i)
+        if (mk[i] == want) G.inst.push_back(i);
+      if (G.inst.empty()) continue;
+      for (int i : G.inst) {
+        const InstHost& I = H->inst[i];
+        G.nmax = std::max(G.nmax, I.ndof);
+        G.n1max = std::max(G.n1max, I.ndof1);
+        G.maxrows = std::max(G.maxrows, inst_maxrows(I));
+        // off-block entries per lane of the prefetched triangular solves: the widest ILUT row
+        // of the group's instances over the 4 lanes per row, rounded up to a power of two
+        const int maxo = inst_max_offblock(I);
+        while (G.ka * 4 < maxo && G.ka < 16) G.ka *= 2;
+      }
+      G.rw = G.ka * 4;
+      lds_plan(G.nmax, G.n1max, G.maxrows, vt, G.ka, dev_lds, G.mask, G.lds_bytes, G.plan);
+      for (int i : G.inst) H->inst_group[i] = (int)H->groups.size();
+      H->groups.push_back(std::move(G));
+    }
   }
-  int maxrows = 1;
+  H->h_instdev.resize(H->ninst);
   for (int i = 0; i < H->ninst; ++i) {
     InstHost& I = H->inst[i];
     InstDev& D = H->h_instdev[i];
+    const pmgrit_handle::Group& G = H->groups[H->inst_group[i]];
     std::memset(&D, 0, sizeof(D));
     D.ndof = I.ndof;
     D.n1 = I.n1;
     D.ndof1 = I.ndof1;
     D.nlev = I.nlev;
     D.nt = I.prob.n_steps;
-    H->nmax = std::max(H->nmax, I.ndof);
-    H->n1max = std::max(H->n1max, I.ndof1);
     D.nin = I.Nin;
     D.p = I.p;
     double* d;
@@ -578,13 +686,13 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
       Dense X1 = I.Mx;
       for (size_t t = 0; t < X1.a.size(); ++t) X1.a[t] = I.Mx.a[t] + Ld.c * I.Kx.a[t];
       TRY(upload_band(H, X1, -p, 2 * p + 1, Ld.X1));
-      TRY(upload_tri(H, Lh.SL, Ld.L, zidx, H->rw));
-      TRY(upload_tri(H, Lh.SU, Ld.U, zidx, H->rw));
+      const int zidx = (G.mask & kY) ? G.plan.zidx : -1;  // prefetched path needs y in LDS
+      TRY(upload_tri(H, Lh.SL, Ld.L, zidx, G.rw));
+      TRY(upload_tri(H, Lh.SU, Ld.U, zidx, G.rw));
       TRY(upload_vec(H, Lh.tl, &d));
       Ld.tl = d;
       TRY(upload_vec(H, Lh.tdinv, &d));
       Ld.tdinv = d;
-      maxrows = std::max(maxrows, std::max(Lh.SL.max_rows, Lh.SU.max_rows));
     }
   }
   TRY(upload_vec(H, H->h_instdev, &H->d_inst));
@@ -606,86 +714,62 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
     }
   TRY(upload_vec(H, H->h_vtab, &H->d_vtab));
   TRY(upload_vec(H, H->h_gtab, &H->d_gtab));
-  // job lists
+  // job lists per group
   const int m = H->m;
-  H->jF.resize(H->nlev);
-  H->jCF.resize(H->nlev);
-  H->jRES.resize(H->nlev);
-  H->res_begin.assign(H->ninst + 1, 0);
-  for (int l = 0; l + 1 < H->nlev; ++l) {
-    std::vector<PhiJob> F, CF, RES;
-    const int Nl = H->Nl[l];
-    for (int i = 0; i < H->ninst; ++i) {
-      for (int j = 0; j * m < Nl; ++j) {
-        int len = std::min(m - 1, Nl - j * m);
-        if (len > 0) F.push_back({i, l, j * m, len, 0, 0});
-        if (j == 0) {
-          if (len > 0) CF.push_back({i, l, 0, len, 0, 0});
+  for (pmgrit_handle::Group& G : H->groups) {
+    G.jF.resize(H->nlev);
+    G.jCF.resize(H->nlev);
+    G.jRES.resize(H->nlev);
+    std::vector<int> res_begin(1, 0);
+    for (int l = 0; l + 1 < H->nlev; ++l) {
+      std::vector<PhiJob> F, CF, RES;
+      const int Nl = H->Nl[l];
+      for (int i : G.inst) {
+        for (int j = 0; j * m < Nl; ++j) {
+          int len = std::min(m - 1, Nl - j * m);
+          if (len > 0) F.push_back({i, l, j * m, len, 0, 0});
+          if (j == 0 && len > 0) CF.push_back({i, l, 0, len, 0, 0});
         }
+        for (int j = 1; j * m <= Nl; ++j) {
+          CF.push_back({i, l, j * m - 1, std::min(m, Nl - j * m + 1), 0, 0});
+          RES.push_back({i, l, j * m - 1, 1, j, 0});
+        }
+        if (l == 0) res_begin.push_back((int)RES.size());
       }
-      for (int j = 1; j * m <= Nl; ++j) {
-        CF.push_back({i, l, j * m - 1, std::min(m, Nl - j * m + 1), 0, 0});
-        RES.push_back({i, l, j * m - 1, 1, j, 0});
-      }
-      if (l == 0) H->res_begin[i + 1] = (int)RES.size();
+      TRY(upload_jobs(H, G, F, G.jF[l]));
+      TRY(upload_jobs(H, G, CF, G.jCF[l]));
+      TRY(upload_jobs(H, G, RES, G.jRES[l]));
     }
-    TRY(upload_jobs(H, F, H->jF[l]));
-    TRY(upload_jobs(H, CF, H->jCF[l]));
-    TRY(upload_jobs(H, RES, H->jRES[l]));
-  }
-  {
     std::vector<PhiJob> C, S;
-    for (int i = 0; i < H->ninst; ++i) {
+    for (int i : G.inst) {
       C.push_back({i, H->nlev - 1, 0, H->Nl[H->nlev - 1], 0, 0});
       S.push_back({i, 0, 0, H->Nt, 0, 0});
     }
-    TRY(upload_jobs(H, C, H->jCoarsest));
-    TRY(upload_jobs(H, S, H->jSeq));
+    TRY(upload_jobs(H, G, C, G.jCoarsest));
+    TRY(upload_jobs(H, G, S, G.jSeq));
+    if (res_begin.size() != G.inst.size() + 1) res_begin.assign(G.inst.size() + 1, 0);
+    TRY(upload_vec(H, res_begin, &G.d_res_begin));
+    TRY(upload_vec(H, G.inst, &G.d_res_inst));
+    // scratch: one slice per workgroup slot; at least kGivenMax slots for pmgrit_phi
+    G.max_jobs = std::max(G.max_jobs, kGivenMax);
+    G.ws_stride = (6 * (int64_t)G.nmax + 32 + 31) / 32 * 32;
+    TRY(upload<double>(H, nullptr, (size_t)G.ws_stride * G.max_jobs, &G.d_ws));
+    TRY(upload<double>(H, nullptr, (size_t)G.max_jobs, &G.d_nrm2));
+    TRY(upload<int>(H, nullptr, (size_t)G.max_jobs, &G.d_vcount));
+    HIPCHK(hipMemset(G.d_vcount, 0, sizeof(int) * G.max_jobs));
+    TRY(upload<PhiJob>(H, nullptr, kGivenMax, &G.d_given_jobs));
+    HIPCHK(hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&G.done, hipEventDisableTiming));
+    HIPCHK(phi_prepare(H->fp32, G.mask, G.lds_bytes));
   }
-  TRY(upload_vec(H, H->res_begin, &H->d_res_begin));
-  // given-mode jobs (pmgrit_phi): up to 4096 right-hand sides
-  H->max_jobs = std::max(H->max_jobs, 4096);
-  TRY(upload<PhiJob>(H, nullptr, 4096, &H->d_given_jobs));
-  // scratch
-  H->ws_stride = 6 * (int64_t)H->nmax + 32;
-  H->ws_stride = (H->ws_stride + 31) / 32 * 32;
-  TRY(upload<double>(H, nullptr, (size_t)H->ws_stride * H->max_jobs, &H->d_ws));
-  TRY(upload<double>(H, nullptr, (size_t)H->max_jobs, &H->d_nrm2));
-  TRY(upload<int>(H, nullptr, (size_t)H->max_jobs, &H->d_vcount));
+  HIPCHK(hipEventCreateWithFlags(&H->fork, hipEventDisableTiming));
   TRY(upload<int>(H, nullptr, 4, &H->d_status));
   TRY(upload<double>(H, nullptr, (size_t)H->ninst, &H->d_resnorm));
-  HIPCHK(hipMemset(H->d_vcount, 0, sizeof(int) * H->max_jobs));
   HIPCHK(hipMemset(H->d_status, 0, sizeof(int) * 4));
   HIPCHK(hipHostMalloc((void**)&H->h_pinned, sizeof(double) * (H->ninst + 8), 0));
-  HIPCHK(hipHostMalloc((void**)&H->h_given_jobs, sizeof(PhiJob) * 4096, 0));
+  HIPCHK(hipHostMalloc((void**)&H->h_given_jobs, sizeof(PhiJob) * kGivenMax, 0));
   H->ev.resize(2048);
   for (auto& e : H->ev) HIPCHK(hipEventCreate(&e));
-  // LDS plan: largest set of work vectors that fits, in the order y, d, s, x.  y is an FP64-sized
-  // slot (it also holds the FP64 Kronecker temporaries and a p = 1 vector), s holds a V-cycle
-  // vector or an FP64 p = 1 vector.
-  int dev_lds = 0;
-  HIPCHK(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, H->device));
-  auto al = [](int b) { return (b + 15) / 16 * 16; };
-  const int base = 512 + al(std::max(maxrows, 256) * vt);  // sbuf: 256 words
-  const int sz_y = al(H->nmax * 8 + 16), sz_d = al(H->nmax * vt), sz_s = al(std::max(H->nmax * vt, H->n1max * 8)),
-            sz_x = al(H->nmax * 8);
-  const int masks[5] = {15, 7, 3, 1, 0};
-  for (int mi = 0; mi < 5; ++mi) {
-    const int mk = masks[mi];
-    int off = base;
-    LdsPlan plan{-1, -1, -1, -1, 512, H->nmax, zidx, H->ka};
-    if (mk & kY) { plan.off_y = off; off += sz_y; }
-    if (mk & kD) { plan.off_d = off; off += sz_d; }
-    if (mk & kS) { plan.off_s = off; off += sz_s; }
-    if (mk & kX) { plan.off_x = off; off += sz_x; }
-    if (off <= dev_lds || mk == 0) {
-      H->mask = mk;
-      H->lds_bytes = off;
-      H->plan = plan;
-      break;
-    }
-  }
-  HIPCHK(phi_prepare(H->fp32, H->mask, H->lds_bytes));
   HIPCHK(hipDeviceSynchronize());
   return PMGRIT_OK;
 }
@@ -694,18 +778,18 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
 // driver
 // ------------------------------------------------------------------------------------------
 
-static PhiParams base_params(pmgrit_handle* H, int mode, const PhiJob* jobs) {
+static PhiParams base_params(pmgrit_handle* H, const pmgrit_handle::Group& G, int mode, const PhiJob* jobs) {
   PhiParams P;
   std::memset(&P, 0, sizeof(P));
   P.inst = H->d_inst;
   P.jobs = jobs;
   P.vtab = H->d_vtab;
   P.gtab = H->d_gtab;
-  P.nrm2 = H->d_nrm2;
-  P.vcount = H->d_vcount;
+  P.nrm2 = G.d_nrm2;
+  P.vcount = G.d_vcount;
   P.status = H->d_status;
-  P.ws = H->d_ws;
-  P.ws_stride = H->ws_stride;
+  P.ws = G.d_ws;
+  P.ws_stride = G.ws_stride;
   P.mode = mode;
   P.guess = H->so.guess == 3 ? 2 : H->so.guess;
   P.maxcyc = H->so.max_vcycles;
@@ -715,7 +799,7 @@ static PhiParams base_params(pmgrit_handle* H, int mode, const PhiJob* jobs) {
   return P;
 }
 
-// accumulate the elapsed times of the recorded event pairs (the stream must be complete)
+// accumulate the elapsed times of the recorded event pairs (their streams must be complete)
 static hipError_t harvest(pmgrit_handle* H) {
   for (int k = 0; k < H->ev_used; ++k) {
     float ms = 0.f;
@@ -727,47 +811,85 @@ static hipError_t harvest(pmgrit_handle* H) {
   return hipSuccess;
 }
 
-static hipError_t phi_timed(pmgrit_handle* H, const PhiParams& P, int nblocks, hipStream_t st) {
-  if (!H->prof) return phi_launch(H->fp32, H->mask, H->lds_bytes, P, H->plan, nblocks, st);
+static hipError_t phi_timed(pmgrit_handle* H, const pmgrit_handle::Group& G, const PhiParams& P, int nblocks,
+                            hipStream_t st) {
+  if (!H->prof) return phi_launch(H->fp32, G.mask, G.lds_bytes, P, G.plan, nblocks, st);
   hipError_t e;
   if (H->ev_used * 2 + 2 > (int)H->ev.size()) {
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
     if ((e = harvest(H)) != hipSuccess) return e;
   }
   const int k = H->ev_used++;
   if ((e = hipEventRecord(H->ev[2 * k], st)) != hipSuccess) return e;
-  if ((e = phi_launch(H->fp32, H->mask, H->lds_bytes, P, H->plan, nblocks, st)) != hipSuccess)
-    return e;
+  if ((e = phi_launch(H->fp32, G.mask, G.lds_bytes, P, G.plan, nblocks, st)) != hipSuccess) return e;
   H->prof_launches++;
   H->prof_wgs += nblocks;
   return hipEventRecord(H->ev[2 * k + 1], st);
 }
 
-static hipError_t launch(pmgrit_handle* H, const pmgrit_handle::JobList& J, int mode, hipStream_t st, int guess = -1) {
-  if (J.n == 0) return hipSuccess;
-  PhiParams P = base_params(H, mode, J.d);
-  if (guess >= 0) P.guess = guess;
-  return phi_timed(H, P, J.n, st);
+// one sweep: the given job list of every group, groups concurrently on their own streams
+// (fork and join through events on the caller's stream)
+template <class Pick>
+static hipError_t sweep(pmgrit_handle* H, Pick pick, int mode, hipStream_t st, int guess = -1) {
+  hipError_t e;
+  int active = 0;
+  for (pmgrit_handle::Group& G : H->groups) active += pick(G).n > 0;
+  if (active == 0) return hipSuccess;
+  const bool fork = active > 1;
+  if (fork && (e = hipEventRecord(H->fork, st)) != hipSuccess) return e;
+  for (pmgrit_handle::Group& G : H->groups) {
+    const pmgrit_handle::JobList& J = pick(G);
+    if (J.n == 0) continue;
+    hipStream_t gs = fork ? G.stream : st;
+    if (fork && (e = hipStreamWaitEvent(gs, H->fork, 0)) != hipSuccess) return e;
+    PhiParams P = base_params(H, G, mode, J.d);
+    if (guess >= 0) P.guess = guess;
+    if ((e = phi_timed(H, G, P, J.n, gs)) != hipSuccess) return e;
+    if (fork && (e = hipEventRecord(G.done, gs)) != hipSuccess) return e;
+  }
+  if (fork)
+    for (pmgrit_handle::Group& G : H->groups)
+      if (pick(G).n > 0 && (e = hipStreamWaitEvent(st, G.done, 0)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+static int64_t sweep_steps(pmgrit_handle* H, int kind, int l) {
+  int64_t s = 0;
+  for (pmgrit_handle::Group& G : H->groups)
+    s += kind == 0 ? G.jF[l].steps : kind == 1 ? G.jCF[l].steps : kind == 2 ? G.jRES[l].steps
+                                                                          : kind == 3 ? G.jCoarsest.steps : G.jSeq.steps;
+  return s;
 }
 
 // one recursive MGRIT cycle at level l >= 1 on A^{(l)} v = g (v zeroed by the caller)
-static hipError_t coarse_cycle(pmgrit_handle* H, int l, hipStream_t st) {
+static hipError_t coarse_cycle(pmgrit_handle* H, int l, hipStream_t st, int64_t& phi) {
   hipError_t e;
-  if (l == H->nlev - 1) return launch(H, H->jCoarsest, kModeChain, st);
-  if ((e = launch(H, H->jF[l], kModeChain, st)) != hipSuccess) return e;
-  if ((e = launch(H, H->jCF[l], kModeChain, st)) != hipSuccess) return e;
-  if ((e = launch(H, H->jRES[l], kModeResidual, st)) != hipSuccess) return e;
+  if (l == H->nlev - 1) {
+    phi += sweep_steps(H, 3, l);
+    return sweep(H, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jCoarsest; }, kModeChain, st);
+  }
+  if ((e = sweep(H, [l](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF[l]; }, kModeChain, st)) !=
+      hipSuccess)
+    return e;
+  if ((e = sweep(H, [l](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jCF[l]; }, kModeChain, st)) !=
+      hipSuccess)
+    return e;
+  if ((e = sweep(H, [l](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jRES[l]; }, kModeResidual,
+                 st)) != hipSuccess)
+    return e;
+  phi += 2 * sweep_steps(H, 0, l) + sweep_steps(H, 1, l) + sweep_steps(H, 2, l);
   for (int i = 0; i < H->ninst; ++i) {
     double* vc = H->h_vtab[(size_t)i * kMaxLevels + l + 1];
     if ((e = fill_launch(vc, (int64_t)(H->Nl[l + 1] + 1) * H->inst[i].ndof, 0.0, st)) != hipSuccess) return e;
   }
-  if ((e = coarse_cycle(H, l + 1, st)) != hipSuccess) return e;
+  if ((e = coarse_cycle(H, l + 1, st, phi)) != hipSuccess) return e;
   for (int i = 0; i < H->ninst; ++i) {
     double* vl = H->h_vtab[(size_t)i * kMaxLevels + l];
     double* vc = H->h_vtab[(size_t)i * kMaxLevels + l + 1];
     if ((e = correct_launch(vl, vc, H->inst[i].ndof, H->m, H->Nl[l + 1], st)) != hipSuccess) return e;
   }
-  return launch(H, H->jF[l], kModeChain, st);  // ideal interpolation = F-relaxation
+  // ideal interpolation = F-relaxation from the corrected C-points
+  return sweep(H, [l](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF[l]; }, kModeChain, st);
 }
 
 static pmgrit_status read_status(pmgrit_handle* H, hipStream_t st) {
@@ -799,11 +921,14 @@ static pmgrit_status begin_solve(pmgrit_handle* H, hipStream_t st, double* const
 }
 
 static int64_t sum_vcycles(pmgrit_handle* H, hipStream_t st) {
-  std::vector<int> v(H->max_jobs);
-  if (hipMemcpyAsync(v.data(), H->d_vcount, sizeof(int) * H->max_jobs, hipMemcpyDeviceToHost, st) != hipSuccess) return -1;
-  if (hipStreamSynchronize(st) != hipSuccess) return -1;
   int64_t s = 0;
-  for (int x : v) s += x;
+  for (pmgrit_handle::Group& G : H->groups) {
+    std::vector<int> v(G.max_jobs);
+    if (hipMemcpyAsync(v.data(), G.d_vcount, sizeof(int) * G.max_jobs, hipMemcpyDeviceToHost, st) != hipSuccess)
+      return -1;
+    if (hipStreamSynchronize(st) != hipSuccess) return -1;
+    for (int x : v) s += x;
+  }
   return s;
 }
 
@@ -843,7 +968,22 @@ pmgrit_status pmgrit_create(int32_t n_instances, const pmgrit_problem* probs, co
     H->Nl.push_back(H->Nl.back() / H->m);
   H->nlev = (int)H->Nl.size();
   H->inst.resize(n_instances);
-  for (int i = 0; i < n_instances; ++i) TRY(setup_instance(H.get(), H->inst[i], probs[i]));
+  {
+    std::string err;
+    pmgrit_status st = parallel_tasks(
+        n_instances,
+        [&](int i, std::string& e) {
+          pmgrit_status r = setup_instance(H.get(), H->inst[i], probs[i]);
+          if (r != PMGRIT_OK) e = "p=1 mass matrix of instance " + std::to_string(i) + " is not SPD";
+          return r;
+        },
+        err);
+    if (st != PMGRIT_OK) return fail(st, err);
+    st = parallel_tasks(
+        n_instances * H->nlev,
+        [&](int t, std::string& e) { return setup_level(H.get(), H->inst[t / H->nlev], t % H->nlev, e); }, err);
+    if (st != PMGRIT_OK) return fail(st, err);
+  }
   if (hip_device >= 0) {
     pmgrit_status s = device_setup(H.get());
     if (s != PMGRIT_OK) {
@@ -868,6 +1008,11 @@ void pmgrit_destroy(pmgrit_handle* h) {
     if (h->h_given_jobs) (void)hipHostFree(h->h_given_jobs);
     for (hipEvent_t e : h->ev)
       if (e) (void)hipEventDestroy(e);
+    for (pmgrit_handle::Group& G : h->groups) {
+      if (G.done) (void)hipEventDestroy(G.done);
+      if (G.stream) (void)hipStreamDestroy(G.stream);
+    }
+    if (h->fork) (void)hipEventDestroy(h->fork);
   }
   delete h;
 }
@@ -975,26 +1120,24 @@ pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* con
   int64_t phi = 0;
   int iters = 0;
   pmgrit_status rc = PMGRIT_OK;
+  auto seq = [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jSeq; };
   if (h->nlev == 1) {
-    HIPCHK(launch(h, h->jSeq, kModeChain, st, h->so.guess == 0 ? 0 : 1));
-    phi += (int64_t)h->Nt * h->ninst;
+    HIPCHK(sweep(h, seq, kModeChain, st, h->so.guess == 0 ? 0 : 1));
+    phi += sweep_steps(h, 4, 0);
   } else {
     std::vector<double> r0(h->ninst, -1.0);
-    auto count_jobs = [&](const pmgrit_handle::JobList& J, bool chain) -> int64_t {
-      (void)chain;
-      return J.n;
-    };
-    (void)count_jobs;
-    // spatial solves per level-0 FCF + residual: N_0 + N_0/m (F, C, F and residual steps)
     for (;;) {
-      HIPCHK(launch(h, h->jF[0], kModeChain, st));
-      HIPCHK(launch(h, h->jCF[0], kModeChain, st));
-      HIPCHK(launch(h, h->jRES[0], kModeResidual, st));
-      HIPCHK(norm_reduce_launch(h->d_nrm2, h->d_res_begin, h->d_resnorm, h->ninst, st));
+      // level-0 F-relaxation, C-relaxation with the following F-relaxation, residual at C-points
+      HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF[0]; }, kModeChain, st));
+      HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jCF[0]; }, kModeChain, st));
+      HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jRES[0]; }, kModeResidual,
+                   st));
+      for (pmgrit_handle::Group& G : h->groups)
+        HIPCHK(norm_reduce_launch(G.d_nrm2, G.d_res_begin, G.d_res_inst, h->d_resnorm, (int)G.inst.size(), st));
       HIPCHK(hipMemcpyAsync(h->h_pinned, h->d_resnorm, sizeof(double) * h->ninst, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       HIPCHK(harvest(h));
-      phi += (int64_t)h->ninst * (2 * h->Nt - h->Nt / h->m + 2 * (h->Nt / h->m));
+      phi += 2 * sweep_steps(h, 0, 0) + sweep_steps(h, 1, 0) + sweep_steps(h, 2, 0);
       bool done = true, bad = false;
       double worst = 0.0;
       for (int i = 0; i < h->ninst; ++i) {
@@ -1024,7 +1167,7 @@ pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* con
         double* vc = h->h_vtab[(size_t)i * kMaxLevels + 1];
         HIPCHK(fill_launch(vc, (int64_t)(h->Nl[1] + 1) * h->inst[i].ndof, 0.0, st));
       }
-      HIPCHK(coarse_cycle(h, 1, st));
+      HIPCHK(coarse_cycle(h, 1, st, phi));
       for (int i = 0; i < h->ninst; ++i) {
         double* vc = h->h_vtab[(size_t)i * kMaxLevels + 1];
         HIPCHK(correct_launch(u_out_dev[i], vc, h->inst[i].ndof, h->m, h->Nl[1], st));
@@ -1051,14 +1194,15 @@ pmgrit_status pmgrit_solve_sequential(pmgrit_handle* h, void* hip_stream, double
   auto t0 = std::chrono::steady_clock::now();
   TRY(begin_solve(h, st, u_out_dev));
   const int64_t vc0 = sum_vcycles(h, st);
-  HIPCHK(launch(h, h->jSeq, kModeChain, st, h->so.guess == 0 ? 0 : 1));
+  HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jSeq; }, kModeChain, st,
+               h->so.guess == 0 ? 0 : 1));
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(harvest(h));
   pmgrit_status rc = read_status(h, st);
   if (stats) {
     pmgrit_stats S;
     std::memset(&S, 0, sizeof(S));
-    S.phi_calls = (int64_t)h->Nt * h->ninst;
+    S.phi_calls = sweep_steps(h, 4, 0);
     S.vcycles = sum_vcycles(h, st) - vc0;
     S.t_setup_s = h->t_setup;
     S.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1069,28 +1213,29 @@ pmgrit_status pmgrit_solve_sequential(pmgrit_handle* h, void* hip_stream, double
 
 pmgrit_status pmgrit_phi(pmgrit_handle* h, int32_t inst, int32_t level, int32_t nrhs, const double* b_dev,
                          double* x_dev, int32_t* vcycles_dev, void* hip_stream) {
-  if (!h || inst < 0 || inst >= h->ninst || level < 0 || level >= h->nlev || nrhs < 0 || nrhs > 4096 ||
+  if (!h || inst < 0 || inst >= h->ninst || level < 0 || level >= h->nlev || nrhs < 0 || nrhs > kGivenMax ||
       (nrhs > 0 && (!b_dev || !x_dev)))
     return fail(PMGRIT_E_ARG, "bad pmgrit_phi arguments");
   if (h->device < 0) return fail(PMGRIT_E_STATE, "host-only handle");
   if (nrhs == 0) return PMGRIT_OK;
   hipStream_t st = (hipStream_t)hip_stream;
   HIPCHK(hipSetDevice(h->device));
+  pmgrit_handle::Group& G = h->groups[h->inst_group[inst]];
   if (h->given_key[0] != inst || h->given_key[1] != level || h->given_key[2] < nrhs) {
     // the pinned staging buffer may still feed an earlier copy: wait before rewriting it
     HIPCHK(hipDeviceSynchronize());
     for (int j = 0; j < nrhs; ++j) h->h_given_jobs[j] = PhiJob{inst, level, 0, 1, 0, 0};
-    HIPCHK(hipMemcpyAsync(h->d_given_jobs, h->h_given_jobs, sizeof(PhiJob) * nrhs, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(G.d_given_jobs, h->h_given_jobs, sizeof(PhiJob) * nrhs, hipMemcpyHostToDevice, st));
     h->given_key[0] = inst;
     h->given_key[1] = level;
     h->given_key[2] = nrhs;
   }
-  PhiParams P = base_params(h, kModeGiven, h->d_given_jobs);
+  PhiParams P = base_params(h, G, kModeGiven, G.d_given_jobs);
   P.vtab = nullptr;
   P.bgiven = b_dev;
   P.xgiven = x_dev;
   P.vlast = vcycles_dev;
-  HIPCHK(phi_timed(h, P, nrhs, st));
+  HIPCHK(phi_timed(h, G, P, nrhs, st));
   return PMGRIT_OK;
 }
 
@@ -1182,14 +1327,31 @@ pmgrit_status pmgrit_info(const pmgrit_handle* h, int64_t* out8) {
   if (!h || !out8) return fail(PMGRIT_E_ARG, "bad info arguments");
   int dev_lds = 0;
   if (h->device >= 0) (void)hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
+  // launch configuration of the first (largest-LDS) group
+  const bool g = !h->groups.empty();
   out8[0] = h->so.precision;
-  out8[1] = h->mask;
-  out8[2] = h->lds_bytes;
+  out8[1] = g ? h->groups[0].mask : -1;
+  out8[2] = g ? h->groups[0].lds_bytes : 0;
   out8[3] = dev_lds;
-  out8[4] = h->ws_stride;
-  out8[5] = h->max_jobs;
+  out8[4] = g ? h->groups[0].ws_stride : 0;
+  out8[5] = g ? h->groups[0].max_jobs : 0;
   out8[6] = h->nlev;
   out8[7] = h->ninst;
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_group_info(const pmgrit_handle* h, int32_t inst, int64_t* out8) {
+  if (!h || !out8 || inst < 0 || inst >= h->ninst) return fail(PMGRIT_E_ARG, "bad group-info arguments");
+  if (h->device < 0) return fail(PMGRIT_E_STATE, "host-only handle");
+  const pmgrit_handle::Group& G = h->groups[h->inst_group[inst]];
+  out8[0] = h->inst_group[inst];
+  out8[1] = (int64_t)h->groups.size();
+  out8[2] = G.mask;
+  out8[3] = G.lds_bytes;
+  out8[4] = G.ka;
+  out8[5] = (int64_t)G.inst.size();
+  out8[6] = G.nmax;
+  out8[7] = G.max_jobs;
   return PMGRIT_OK;
 }
 

@@ -596,8 +596,10 @@ __global__ void correct_kernel(double* __restrict__ Vl, const double* __restrict
 }
 
 // per instance: sum of the residual norms of its workgroups [begin[i], begin[i+1])
+// ||r||^2 per instance from the per-workgroup partial sums of one group: workgroups
+// begin[i] .. begin[i+1]-1 belong to the group's i-th instance, whose global id is id[i]
 __global__ void norm_reduce_kernel(const double* __restrict__ nrm2, const int* __restrict__ begin,
-                                   double* __restrict__ out) {
+                                   const int* __restrict__ id, double* __restrict__ out) {
   __shared__ double red[4];
   const int i = blockIdx.x;
   double s = 0.0;
@@ -608,7 +610,7 @@ __global__ void norm_reduce_kernel(const double* __restrict__ nrm2, const int* _
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int w = 0; w < (int)(blockDim.x / 64); ++w) t += red[w];
-    out[i] = t;
+    out[id[i]] = t;
   }
 }
 
@@ -666,8 +668,9 @@ hipError_t correct_launch(double* Vl, const double* Vc, int ndof, int m, int nco
   return hipGetLastError();
 }
 
-hipError_t norm_reduce_launch(const double* nrm2, const int* begin, double* out, int ninst, hipStream_t st) {
-  hipLaunchKernelGGL(norm_reduce_kernel, dim3(ninst), dim3(256), 0, st, nrm2, begin, out);
+hipError_t norm_reduce_launch(const double* nrm2, const int* begin, const int* id, double* out, int ninst,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(norm_reduce_kernel, dim3(ninst), dim3(256), 0, st, nrm2, begin, id, out);
   return hipGetLastError();
 }
 
