@@ -131,6 +131,21 @@ def traffic_for(kernel_src_hash: str):
     return rec
 
 
+def copy_calibration(mib: int = 512, reps: int = 4):
+    """A plain device copy of known size, for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters
+    (each dispatch reads and writes exactly `mib` MiB)."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_dispatch": n * 4, "dispatches": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +153,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--variants", default="fp64,fp32")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 512 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1"}))
@@ -147,6 +164,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     variants = {}
     finals = {}
     for v in args.variants.split(","):
