@@ -30,6 +30,22 @@ def random_modes(seed: int, n_modes: int = 8, kmax: int = 6):
     return [(int(pairs[i][0]), int(pairs[i][1]), float(a)) for i, a in zip(sel, amps)]
 
 
+def net_init(seed: int, zero_last: bool = False):
+    """Seeded initial parameters of the warm-start network (flat float64 array, layer by layer:
+    weights [cout][cin][3][3] then bias [cout], channels 3 -> 32 -> 32 -> 32 -> 1): He-scaled normal
+    weights (the last layer scaled by 0.1, or zero with zero_last), zero biases."""
+    rng = np.random.default_rng(seed)
+    ch = [3, 32, 32, 32, 1]
+    parts = []
+    for l in range(4):
+        ci, co = ch[l], ch[l + 1]
+        w = rng.standard_normal(co * ci * 9) * np.sqrt(2.0 / (9 * ci))
+        if l == 3:
+            w = np.zeros_like(w) if zero_last else 0.1 * w
+        parts += [w, np.zeros(co)]
+    return np.concatenate(parts)
+
+
 def manufactured(kappa: float = 1.0):
     """source modes, time kind and initial modes of u = sin(pi x) sin(pi y) e^{-t}"""
     return [(1, 1, 2.0 * np.pi ** 2 * kappa - 1.0)], 1, [(1, 1, 1.0)]
