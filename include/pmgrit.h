@@ -83,8 +83,11 @@ typedef struct {
 /* Spatial solver (Sec. 4).  precision 0: FP64 V-cycle.  precision 1: V-cycle in FP32 as the
  * preconditioner of FP64 iterative refinement (residual, update and the p = 1 solve in FP64).
  * guess: initial iterate of every spatial solve -- 0 zero, 1 previous time point,
- * 2 current value of the target point (MGRIT), 3 learned warm start (network, see
- * pmgrit_net_load; falls back to the better of 1 and 2 by FP64 residual).
+ * 2 current value of the target point (MGRIT), 3 learned warm start: the network's prediction
+ * from the previous point, or the previous point itself if its FP64 residual is smaller (needs
+ * pmgrit_net_load before solving).  With guess 3, sequential stepping predicts every step;
+ * MGRIT predicts the level-0 F- and C-relaxation steps of its first iteration, step by step, and
+ * uses guess 2 afterwards.
  * trsv_block: row-block size of the blocked triangular solves (0 = autotune,
  * 1 = plain row level-scheduling, -1 = one grid line). */
 typedef struct {
@@ -179,30 +182,67 @@ pmgrit_status pmgrit_host_schedule(const pmgrit_handle* h, int32_t inst, int32_t
 pmgrit_status pmgrit_host_coarse_solve(const pmgrit_handle* h, int32_t inst, int32_t level, const double* b,
                                        double* x);
 
-/* Learned warm start (not part of the paper): a 4-layer 3x3 convolutional network over the
- * (n+p) x (n+p) coefficient grid with channels 3 -> 32 -> 32 -> 32 -> 1 (inputs u_k, the
- * load vector and log dt as planes; ReLU between layers; the output is added to u_k).
- * Weights are a flat host array of float (FP32 master copy; the kernels use BF16 copies):
- * per layer weights [cout][cin][3][3] then bias [cout]; pmgrit_net_nparams gives the count. */
+/* Learned warm start (not part of the paper).  A 4-layer 3x3 convolutional network over the
+ * G x G tensor-product coefficient grid (G = n + p, the Dirichlet ring included) with channels
+ * 3 -> 32 -> 32 -> 32 -> 1, zero padding and ReLU after the first three layers.  Input planes of
+ * a sample (step k -> k + 1 of an instance, time level l): u_k / s, (dt_l F / m) / s with m the
+ * row-sum-lumped mass, and ln(kappa dt_l n^2) / 4; s = rms(u_k) + rms(dt_l F / m) over the
+ * interior (1 if both vanish).  Output y: guess u_{k+1} = u_k + s y on the interior; training
+ * target t = (u_{k+1} - u_k) / s; loss = mean over samples and interior points of (y - t)^2.
+ * Weights, inputs and hidden activations (and hidden gradients) are BF16 with FP32 accumulation.
+ * Parameters: a flat float array, per layer weights [cout][cin][3][3] then bias [cout]
+ * (pmgrit_net_nparams() floats, FP32 master copy).  A handle holds one network. */
 int64_t pmgrit_net_nparams(void);
+
+/* Load (and reset the optimiser state) / save the parameters.  Errors: PMGRIT_E_ARG when n is not
+ * pmgrit_net_nparams() or a pointer is NULL, PMGRIT_E_STATE for a host-only handle or (save) no
+ * network loaded. */
 pmgrit_status pmgrit_net_load(pmgrit_handle* h, const float* weights_host, int64_t n);
 pmgrit_status pmgrit_net_save(const pmgrit_handle* h, float* weights_host, int64_t n);
 
-/* Network inference on a batch: x_dev (nb x 3 x G x G float) -> y_dev (nb x G x G float),
- * G = grid_n of instance inst, BF16 weights and FP32 accumulation on the matrix cores. */
-pmgrit_status pmgrit_net_forward(pmgrit_handle* h, int32_t inst, int32_t nb, const float* x_dev, float* y_dev,
+/* Network inference on given planes: x_dev (nb x 3 x G x G float, device) -> y_dev (nb x G x G
+ * float, device), asynchronous on hip_stream.  3 <= G <= 1024, 1 <= nb. */
+pmgrit_status pmgrit_net_forward(pmgrit_handle* h, int32_t G, int32_t nb, const float* x_dev, float* y_dev,
                                  void* hip_stream);
 
-/* One training step (Adam, lr, betas 0.9/0.999, eps 1e-8) on a batch with targets t_dev
- * (nb x G x G float), mean-squared-error loss; loss_host receives the batch loss.  The
- * gradients come from the library's own backward kernels. */
-pmgrit_status pmgrit_net_train_step(pmgrit_handle* h, int32_t inst, int32_t nb, const float* x_dev,
-                                    const float* t_dev, float lr, float* loss_host, void* hip_stream);
+/* Loss and gradient for given planes and targets t_dev (nb x G x G float, device), computed by the
+ * library's backward kernels; grad_host (pmgrit_net_nparams() floats) and loss_host may be NULL.
+ * Synchronises hip_stream. */
+pmgrit_status pmgrit_net_grad(pmgrit_handle* h, int32_t G, int32_t nb, const float* x_dev, const float* t_dev,
+                              float* grad_host, double* loss_host, void* hip_stream);
 
-/* Gradients of the mean-squared-error loss for a batch, written to grad_host (nparams
- * floats), for checking against a CPU reference. */
-pmgrit_status pmgrit_net_grad(pmgrit_handle* h, int32_t inst, int32_t nb, const float* x_dev, const float* t_dev,
-                              float* grad_host, float* loss_host, void* hip_stream);
+/* One Adam step (betas 0.9 / 0.999, eps 1e-8, bias-corrected) on given planes and targets;
+ * loss_host (may be NULL) receives the batch loss before the step.  Synchronises hip_stream. */
+pmgrit_status pmgrit_net_train_step(pmgrit_handle* h, int32_t G, int32_t nb, const float* x_dev, const float* t_dev,
+                                    float lr, double* loss_host, void* hip_stream);
+
+/* Input planes (x_dev, nb x 3 x G x G), targets (t_dev, may be NULL) and scales (s_dev, nb doubles)
+ * of the samples (inst, k_host[j] -> k_host[j] + 1) at time level `level`, read from the
+ * trajectory U_dev ((N_l + 1) x n_dof doubles, device) of instance inst.  0 <= k < N_t
+ * (k + 1 <= N_t is read only when t_dev is given).  Asynchronous on hip_stream. */
+pmgrit_status pmgrit_net_pack(pmgrit_handle* h, int32_t inst, int32_t level, int32_t nb, const int32_t* k_host,
+                              const double* U_dev, float* x_dev, float* t_dev, double* s_dev, void* hip_stream);
+
+typedef struct {
+  int32_t epochs;   /* passes over all (instance, step) samples */
+  int32_t batch;    /* samples per Adam step (>= 1) */
+  float lr;         /* Adam learning rate */
+  uint32_t seed;    /* shuffling (counter-based hash of (seed, epoch, index)) */
+} pmgrit_train_opts;
+
+typedef struct {
+  int32_t epochs_done;
+  int64_t adam_steps;
+  double loss_first;  /* loss of the first batch */
+  double loss_last;   /* mean loss over the last epoch's batches */
+  double seconds;
+} pmgrit_train_stats;
+
+/* Train the handle's network (from its loaded parameters) on the level-0 steps of trajectories the
+ * solver produced: U_dev[i] is instance i's (N_t + 1) x n_dof trajectory (device).  Every instance
+ * must have the same grid size G.  Synchronous. */
+pmgrit_status pmgrit_net_train(pmgrit_handle* h, const pmgrit_train_opts* opts, const double* const* U_dev,
+                               void* hip_stream, pmgrit_train_stats* stats);
 
 /* Launch configuration chosen at create for the first launch group (for logs and tests):
  * out8 = {precision, LDS placement mask (bit 0 triangular-solve vector y, 1 V-cycle correction

@@ -51,6 +51,15 @@ class Stats(C.Structure):
                     vcycles=self.vcycles, t_setup_s=self.t_setup_s, t_solve_s=self.t_solve_s)
 
 
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("seed", C.c_uint32)]
+
+
+class TrainStats(C.Structure):
+    _fields_ = [("epochs_done", C.c_int32), ("adam_steps", C.c_int64), ("loss_first", C.c_double),
+                ("loss_last", C.c_double), ("seconds", C.c_double)]
+
+
 _lib = None
 _vp = C.c_void_p
 _dp = C.POINTER(C.c_double)
@@ -89,8 +98,10 @@ def lib():
         L.pmgrit_net_load.argtypes = [_vp, _fp, C.c_int64]
         L.pmgrit_net_save.argtypes = [_vp, _fp, C.c_int64]
         L.pmgrit_net_forward.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp]
-        L.pmgrit_net_train_step.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, C.c_float, _fp, _vp]
-        L.pmgrit_net_grad.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _fp, _fp, _vp]
+        L.pmgrit_net_grad.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, _fp, _dp, _vp]
+        L.pmgrit_net_train_step.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _vp, C.c_float, _dp, _vp]
+        L.pmgrit_net_pack.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int32, _ip, _vp, _vp, _vp, _vp, _vp]
+        L.pmgrit_net_train.argtypes = [_vp, C.POINTER(TrainOpts), C.POINTER(_vp), _vp, C.POINTER(TrainStats)]
         L.pmgrit_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -250,6 +261,66 @@ class Solver:
         vc = _dptr(vcycles) if vcycles is not None else _vp()
         _check(lib().pmgrit_phi(self._h, inst, level, nrhs, _dptr(b), _dptr(x), vc, _vp(_stream_ptr(stream))))
         return x
+
+    # ---- learned warm start ----
+    @staticmethod
+    def net_nparams() -> int:
+        return int(lib().pmgrit_net_nparams())
+
+    def net_load(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        _check(lib().pmgrit_net_load(self._h, th.ctypes.data_as(_fp), th.size))
+
+    def net_save(self):
+        th = np.zeros(self.net_nparams(), dtype=np.float32)
+        _check(lib().pmgrit_net_save(self._h, th.ctypes.data_as(_fp), th.size))
+        return th
+
+    def net_forward(self, x, y=None, stream=None):
+        """x: (nb, 3, G, G) float32 CUDA tensor -> y (nb, G, G)."""
+        import torch
+        nb, _, G, _ = x.shape
+        y = y if y is not None else torch.empty((nb, G, G), dtype=torch.float32, device=x.device)
+        _check(lib().pmgrit_net_forward(self._h, G, nb, _dptr(x), _dptr(y), _vp(_stream_ptr(stream))))
+        return y
+
+    def net_grad(self, x, t, stream=None):
+        nb, _, G, _ = x.shape
+        g = np.zeros(self.net_nparams(), dtype=np.float32)
+        loss = C.c_double()
+        _check(lib().pmgrit_net_grad(self._h, G, nb, _dptr(x), _dptr(t), g.ctypes.data_as(_fp), C.byref(loss),
+                                     _vp(_stream_ptr(stream))))
+        return loss.value, g
+
+    def net_train_step(self, x, t, lr: float, stream=None):
+        nb, _, G, _ = x.shape
+        loss = C.c_double()
+        _check(lib().pmgrit_net_train_step(self._h, G, nb, _dptr(x), _dptr(t), lr, C.byref(loss),
+                                           _vp(_stream_ptr(stream))))
+        return loss.value
+
+    def net_pack(self, inst: int, level: int, ks, U, with_target: bool = True, stream=None):
+        """Planes (nb, 3, G, G), targets (nb, G, G) or None, scales (nb,) of samples (inst, k -> k+1)."""
+        import torch
+        ks = np.ascontiguousarray(ks, dtype=np.int32)
+        nb = ks.size
+        p = self.problems[inst]
+        G = p.n_elems + p.degree_p
+        dev = U.device
+        x = torch.empty((nb, 3, G, G), dtype=torch.float32, device=dev)
+        t = torch.empty((nb, G, G), dtype=torch.float32, device=dev) if with_target else None
+        s = torch.empty(nb, dtype=torch.float64, device=dev)
+        _check(lib().pmgrit_net_pack(self._h, inst, level, nb, ks.ctypes.data_as(_ip), _dptr(U), _dptr(x),
+                                     _dptr(t) if t is not None else _vp(), _dptr(s), _vp(_stream_ptr(stream))))
+        return x, t, s
+
+    def net_train(self, trajectories, epochs: int, batch: int, lr: float, seed: int = 0, stream=None):
+        o = TrainOpts(epochs=epochs, batch=batch, lr=lr, seed=seed)
+        st = TrainStats()
+        ptrs = (_vp * self.n)(*[_dptr(u) for u in trajectories])
+        _check(lib().pmgrit_net_train(self._h, C.byref(o), ptrs, _vp(_stream_ptr(stream)), C.byref(st)))
+        return dict(epochs=st.epochs_done, adam_steps=st.adam_steps, loss_first=st.loss_first,
+                    loss_last=st.loss_last, seconds=st.seconds)
 
     # ---- host inspection ----
     MATS = {"M": 0, "K": 1, "A": 2, "L": 3, "U": 4, "P": 5, "M1": 6, "K1": 7}

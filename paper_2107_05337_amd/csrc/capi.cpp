@@ -16,6 +16,7 @@
 #include "../../include/pmgrit.h"
 #include "device_types.hpp"
 #include "host_setup.hpp"
+#include "net.hpp"
 
 namespace pmg {
 hipError_t phi_prepare(int fp32, int mask, int lds_bytes);
@@ -108,6 +109,10 @@ struct pmgrit_handle {
     LdsPlan plan{-1, -1, -1, -1, 512, 0, 0, 2};
     std::vector<JobList> jF, jCF, jRES;
     JobList jCoarsest, jSeq;
+    // single-step lists of the learned warm start: level-0 F steps per position s in the
+    // interval, level-0 C steps, and one step per instance (sequential stepping, shifted by k)
+    std::vector<JobList> jF1;
+    JobList jC1, jSeq1;
     int max_jobs = 0;
     double* d_ws = nullptr;
     int64_t ws_stride = 0;
@@ -121,6 +126,22 @@ struct pmgrit_handle {
   };
   std::vector<Group> groups;
   std::vector<int> inst_group;
+  // learned warm start: the network and, per grid size, the samples of the single-step lists
+  std::unique_ptr<NetState> net;
+  struct NetGroup {
+    int G = 0;
+    std::vector<int> inst;
+    NetPick* d_seq = nullptr;  // (i, 0) per instance, shifted by k
+    std::vector<NetPick*> d_f;  // per s: level-0 F steps (i, j m + s)
+    std::vector<int> nf;
+    NetPick* d_c = nullptr;  // level-0 C steps (i, j m - 1)
+    int nc = 0;
+  };
+  std::vector<NetGroup> ngroups;
+  NetSrc* d_netsrc = nullptr;
+  NetSrc* h_netsrc = nullptr;  // pinned staging
+  NetSrc* d_src_tmp = nullptr;
+  NetPick* d_pick_tmp = nullptr;
   hipEvent_t fork = nullptr;
   // live kernel timing
   bool prof = false;
@@ -604,6 +625,81 @@ static int inst_max_offblock(const InstHost& I) {
   return maxo;
 }
 
+// sample sources and single-step job / sample lists of the learned warm start
+static pmgrit_status learned_setup(pmgrit_handle* H) {
+  HIPCHK(hipHostMalloc((void**)&H->h_netsrc, sizeof(NetSrc) * H->ninst, 0));
+  for (int i = 0; i < H->ninst; ++i) {
+    const InstHost& I = H->inst[i];
+    const InstDev& D = H->h_instdev[i];
+    NetSrc& S = H->h_netsrc[i];
+    std::memset(&S, 0, sizeof(S));
+    S.F = D.F;
+    S.ilx = D.ilp_x;
+    S.ily = D.ilp_y;
+    S.dt = I.lev[0].dt;
+    S.lnc = std::log(I.prob.kappa * S.dt * (double)I.prob.n_elems * (double)I.prob.n_elems) / 4.0;
+    S.nin = I.Nin;
+    S.G = I.Nin + 2;
+  }
+  TRY(upload<NetSrc>(H, nullptr, (size_t)H->ninst, &H->d_netsrc));
+  TRY(upload<NetSrc>(H, nullptr, 1, &H->d_src_tmp));
+  TRY(upload<NetPick>(H, nullptr, kGivenMax, &H->d_pick_tmp));
+  if (H->so.guess != 3) return PMGRIT_OK;
+  const int m = H->m, N0 = H->Nl[0];
+  auto fsteps = [&](int i, int s, auto emit) {
+    for (int j = 0; j * m + s + 1 <= N0 && s + 1 < m; ++j) emit(i, j * m + s);
+  };
+  auto csteps = [&](int i, auto emit) {
+    for (int j = 1; j * m <= N0; ++j) emit(i, j * m - 1);
+  };
+  for (pmgrit_handle::Group& G : H->groups) {
+    G.jF1.resize(std::max(m - 1, 1));
+    for (int s = 0; s + 1 < m; ++s) {
+      std::vector<PhiJob> J;
+      for (int i : G.inst) fsteps(i, s, [&](int ii, int k) { J.push_back({ii, 0, k, 1, 0, 0}); });
+      TRY(upload_jobs(H, G, J, G.jF1[s]));
+    }
+    std::vector<PhiJob> C, S1;
+    for (int i : G.inst) {
+      csteps(i, [&](int ii, int k) { C.push_back({ii, 0, k, 1, 0, 0}); });
+      S1.push_back({i, 0, 0, 1, 0, 0});
+    }
+    TRY(upload_jobs(H, G, C, G.jC1));
+    TRY(upload_jobs(H, G, S1, G.jSeq1));
+  }
+  // network batches: instances of one grid size
+  for (int i = 0; i < H->ninst; ++i) {
+    const int Gi = H->inst[i].Nin + 2;
+    auto it = std::find_if(H->ngroups.begin(), H->ngroups.end(),
+                           [Gi](const pmgrit_handle::NetGroup& N) { return N.G == Gi; });
+    if (it == H->ngroups.end()) {
+      H->ngroups.emplace_back();
+      H->ngroups.back().G = Gi;
+      it = H->ngroups.end() - 1;
+    }
+    it->inst.push_back(i);
+  }
+  for (pmgrit_handle::NetGroup& N : H->ngroups) {
+    std::vector<NetPick> seq, c;
+    for (int i : N.inst) {
+      seq.push_back({i, 0});
+      csteps(i, [&](int ii, int k) { c.push_back({ii, k}); });
+    }
+    TRY(upload_vec(H, seq, &N.d_seq));
+    TRY(upload_vec(H, c, &N.d_c));
+    N.nc = (int)c.size();
+    N.d_f.assign(std::max(m - 1, 1), nullptr);
+    N.nf.assign(std::max(m - 1, 1), 0);
+    for (int s = 0; s + 1 < m; ++s) {
+      std::vector<NetPick> f;
+      for (int i : N.inst) fsteps(i, s, [&](int ii, int k) { f.push_back({ii, k}); });
+      TRY(upload_vec(H, f, &N.d_f[s]));
+      N.nf[s] = (int)f.size();
+    }
+  }
+  return PMGRIT_OK;
+}
+
 static pmgrit_status device_setup(pmgrit_handle* H) {
   HIPCHK(hipSetDevice(H->device));
   H->fp32 = H->so.precision == 1;
@@ -762,6 +858,7 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
     HIPCHK(hipEventCreateWithFlags(&G.done, hipEventDisableTiming));
     HIPCHK(phi_prepare(H->fp32, G.mask, G.lds_bytes));
   }
+  TRY(learned_setup(H));
   HIPCHK(hipEventCreateWithFlags(&H->fork, hipEventDisableTiming));
   TRY(upload<int>(H, nullptr, 4, &H->d_status));
   TRY(upload<double>(H, nullptr, (size_t)H->ninst, &H->d_resnorm));
@@ -830,7 +927,7 @@ static hipError_t phi_timed(pmgrit_handle* H, const pmgrit_handle::Group& G, con
 // one sweep: the given job list of every group, groups concurrently on their own streams
 // (fork and join through events on the caller's stream)
 template <class Pick>
-static hipError_t sweep(pmgrit_handle* H, Pick pick, int mode, hipStream_t st, int guess = -1) {
+static hipError_t sweep(pmgrit_handle* H, Pick pick, int mode, hipStream_t st, int guess = -1, int kshift = 0) {
   hipError_t e;
   int active = 0;
   for (pmgrit_handle::Group& G : H->groups) active += pick(G).n > 0;
@@ -844,6 +941,7 @@ static hipError_t sweep(pmgrit_handle* H, Pick pick, int mode, hipStream_t st, i
     if (fork && (e = hipStreamWaitEvent(gs, H->fork, 0)) != hipSuccess) return e;
     PhiParams P = base_params(H, G, mode, J.d);
     if (guess >= 0) P.guess = guess;
+    P.kshift = kshift;
     if ((e = phi_timed(H, G, P, J.n, gs)) != hipSuccess) return e;
     if (fork && (e = hipEventRecord(G.done, gs)) != hipSuccess) return e;
   }
@@ -859,6 +957,19 @@ static int64_t sweep_steps(pmgrit_handle* H, int kind, int l) {
     s += kind == 0 ? G.jF[l].steps : kind == 1 ? G.jCF[l].steps : kind == 2 ? G.jRES[l].steps
                                                                           : kind == 3 ? G.jCoarsest.steps : G.jSeq.steps;
   return s;
+}
+
+// learned guesses written into the targets of a single-step list: which 0 sequential (shifted by
+// kbase), 1 level-0 F steps at position s, 2 level-0 C steps
+static hipError_t net_predict(pmgrit_handle* H, int which, int s, int kbase, hipStream_t st) {
+  for (pmgrit_handle::NetGroup& N : H->ngroups) {
+    const NetPick* pk = which == 0 ? N.d_seq : which == 1 ? N.d_f[s] : N.d_c;
+    const int nb = which == 0 ? (int)N.inst.size() : which == 1 ? N.nf[s] : N.nc;
+    if (nb == 0) continue;
+    hipError_t e = H->net->predict(H->d_netsrc, pk, kbase, nb, N.G, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // one recursive MGRIT cycle at level l >= 1 on A^{(l)} v = g (v zeroed by the caller)
@@ -910,6 +1021,14 @@ static pmgrit_status begin_solve(pmgrit_handle* H, hipStream_t st, double* const
     H->h_vtab[(size_t)i * kMaxLevels] = u_out[i];
   }
   HIPCHK(hipMemcpyAsync(H->d_vtab, H->h_vtab.data(), sizeof(double*) * H->h_vtab.size(), hipMemcpyHostToDevice, st));
+  if (H->so.guess == 3) {
+    if (!H->net || !H->net->loaded) return fail(PMGRIT_E_STATE, "guess 3 needs a network: call pmgrit_net_load");
+    for (int i = 0; i < H->ninst; ++i) {
+      H->h_netsrc[i].U = u_out[i];
+      H->h_netsrc[i].Uout = u_out[i];
+    }
+    HIPCHK(hipMemcpyAsync(H->d_netsrc, H->h_netsrc, sizeof(NetSrc) * H->ninst, hipMemcpyHostToDevice, st));
+  }
   HIPCHK(hipMemsetAsync(H->d_status, 0, sizeof(int) * 4, st));
   // initial iterate: U_0 = u0, U_k = 0 for k >= 1
   for (int i = 0; i < H->ninst; ++i) {
@@ -1006,6 +1125,8 @@ void pmgrit_destroy(pmgrit_handle* h) {
     for (void* p : h->allocs) (void)hipFree(p);
     if (h->h_pinned) (void)hipHostFree(h->h_pinned);
     if (h->h_given_jobs) (void)hipHostFree(h->h_given_jobs);
+    if (h->h_netsrc) (void)hipHostFree(h->h_netsrc);
+    h->net.reset();
     for (hipEvent_t e : h->ev)
       if (e) (void)hipEventDestroy(e);
     for (pmgrit_handle::Group& G : h->groups) {
@@ -1128,8 +1249,27 @@ pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* con
     std::vector<double> r0(h->ninst, -1.0);
     for (;;) {
       // level-0 F-relaxation, C-relaxation with the following F-relaxation, residual at C-points
-      HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF[0]; }, kModeChain, st));
-      HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jCF[0]; }, kModeChain, st));
+      if (h->so.guess == 3 && iters == 0) {
+        // first iteration with learned guesses: the same relaxations one step position at a
+        // time, each preceded by the network's predictions for its targets
+        auto fsplit = [&]() -> hipError_t {
+          for (int s = 0; s + 1 < h->m; ++s) {
+            hipError_t e = net_predict(h, 1, s, 0, st);
+            if (e == hipSuccess)
+              e = sweep(h, [s](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF1[s]; }, kModeChain,
+                        st, 4);
+            if (e != hipSuccess) return e;
+          }
+          return hipSuccess;
+        };
+        HIPCHK(fsplit());
+        HIPCHK(net_predict(h, 2, 0, 0, st));
+        HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jC1; }, kModeChain, st, 4));
+        HIPCHK(fsplit());
+      } else {
+        HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF[0]; }, kModeChain, st));
+        HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jCF[0]; }, kModeChain, st));
+      }
       HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jRES[0]; }, kModeResidual,
                    st));
       for (pmgrit_handle::Group& G : h->groups)
@@ -1194,8 +1334,18 @@ pmgrit_status pmgrit_solve_sequential(pmgrit_handle* h, void* hip_stream, double
   auto t0 = std::chrono::steady_clock::now();
   TRY(begin_solve(h, st, u_out_dev));
   const int64_t vc0 = sum_vcycles(h, st);
-  HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jSeq; }, kModeChain, st,
-               h->so.guess == 0 ? 0 : 1));
+  if (h->so.guess == 3) {
+    // one launch per step: predictions, then the solves starting from the better of the
+    // prediction and the previous point
+    for (int k = 0; k < h->Nt; ++k) {
+      HIPCHK(net_predict(h, 0, 0, k, st));
+      HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jSeq1; }, kModeChain, st, 4,
+                   k));
+    }
+  } else {
+    HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jSeq; }, kModeChain, st,
+                 h->so.guess == 0 ? 0 : 1));
+  }
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(harvest(h));
   pmgrit_status rc = read_status(h, st);
@@ -1352,6 +1502,169 @@ pmgrit_status pmgrit_group_info(const pmgrit_handle* h, int32_t inst, int64_t* o
   out8[5] = (int64_t)G.inst.size();
   out8[6] = G.nmax;
   out8[7] = G.max_jobs;
+  return PMGRIT_OK;
+}
+
+static pmgrit_status net_ready(pmgrit_handle* h) {
+  if (h->device < 0) return fail(PMGRIT_E_STATE, "host-only handle");
+  HIPCHK(hipSetDevice(h->device));
+  if (!h->net) {
+    std::unique_ptr<NetState> n(new NetState());
+    HIPCHK(n->init(h->device));
+    h->net = std::move(n);
+  }
+  return PMGRIT_OK;
+}
+
+int64_t pmgrit_net_nparams(void) { return kNetParams; }
+
+pmgrit_status pmgrit_net_load(pmgrit_handle* h, const float* weights_host, int64_t n) {
+  if (!h || !weights_host || n != kNetParams) return fail(PMGRIT_E_ARG, "bad network parameters");
+  TRY(net_ready(h));
+  HIPCHK(h->net->load(weights_host));
+  // buffers for the solve paths' batches, so solving allocates nothing
+  for (const pmgrit_handle::NetGroup& N : h->ngroups) {
+    int nb = std::max((int)N.inst.size(), N.nc);
+    for (int x : N.nf) nb = std::max(nb, x);
+    HIPCHK(h->net->reserve(nb, N.G));
+  }
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_net_save(const pmgrit_handle* h, float* weights_host, int64_t n) {
+  if (!h || !weights_host || n != kNetParams) return fail(PMGRIT_E_ARG, "bad network parameters");
+  if (h->device < 0 || !h->net || !h->net->loaded) return fail(PMGRIT_E_STATE, "no network loaded");
+  HIPCHK(hipSetDevice(h->device));
+  HIPCHK(h->net->save(weights_host));
+  return PMGRIT_OK;
+}
+
+static pmgrit_status net_args(pmgrit_handle* h, int32_t G, int32_t nb, const void* x, const void* y) {
+  if (!h || G < 3 || G > 1024 || nb < 1 || !x || !y) return fail(PMGRIT_E_ARG, "bad network arguments");
+  TRY(net_ready(h));
+  if (!h->net->loaded) return fail(PMGRIT_E_STATE, "no network loaded");
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_net_forward(pmgrit_handle* h, int32_t G, int32_t nb, const float* x_dev, float* y_dev,
+                                 void* hip_stream) {
+  TRY(net_args(h, G, nb, x_dev, y_dev));
+  HIPCHK(h->net->forward(nb, G, x_dev, y_dev, (hipStream_t)hip_stream));
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_net_grad(pmgrit_handle* h, int32_t G, int32_t nb, const float* x_dev, const float* t_dev,
+                              float* grad_host, double* loss_host, void* hip_stream) {
+  TRY(net_args(h, G, nb, x_dev, t_dev));
+  HIPCHK(h->net->loss_and_grad(nb, G, x_dev, t_dev, grad_host, loss_host, (hipStream_t)hip_stream));
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_net_train_step(pmgrit_handle* h, int32_t G, int32_t nb, const float* x_dev, const float* t_dev,
+                                    float lr, double* loss_host, void* hip_stream) {
+  TRY(net_args(h, G, nb, x_dev, t_dev));
+  if (!(lr >= 0.f)) return fail(PMGRIT_E_ARG, "bad learning rate");
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIPCHK(h->net->backward(nb, G, x_dev, t_dev, st));
+  HIPCHK(h->net->adam_step(lr, st));
+  if (loss_host) HIPCHK(h->net->read_loss(loss_host, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_net_pack(pmgrit_handle* h, int32_t inst, int32_t level, int32_t nb, const int32_t* k_host,
+                              const double* U_dev, float* x_dev, float* t_dev, double* s_dev, void* hip_stream) {
+  if (!h || inst < 0 || inst >= h->ninst || level < 0 || level >= h->nlev || nb < 1 || nb > kGivenMax || !k_host ||
+      !U_dev || !x_dev || !s_dev)
+    return fail(PMGRIT_E_ARG, "bad pack arguments");
+  const int lim = h->Nl[level] - (t_dev ? 1 : 0);
+  for (int j = 0; j < nb; ++j)
+    if (k_host[j] < 0 || k_host[j] > lim) return fail(PMGRIT_E_ARG, "step index out of range");
+  TRY(net_ready(h));
+  hipStream_t st = (hipStream_t)hip_stream;
+  const InstHost& I = h->inst[inst];
+  NetSrc S = h->h_netsrc[inst];
+  S.U = U_dev;
+  S.Uout = nullptr;
+  S.dt = I.lev[level].dt;
+  S.lnc = std::log(I.prob.kappa * S.dt * (double)I.prob.n_elems * (double)I.prob.n_elems) / 4.0;
+  std::vector<NetPick> pk(nb);
+  for (int j = 0; j < nb; ++j) pk[j] = {0, k_host[j]};
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipMemcpy(h->d_src_tmp, &S, sizeof(S), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->d_pick_tmp, pk.data(), sizeof(NetPick) * nb, hipMemcpyHostToDevice));
+  const int G = S.G;
+  HIPCHK(h->net->pack(h->d_src_tmp, h->d_pick_tmp, 0, nb, G, t_dev != nullptr, st));
+  const size_t pl = (size_t)nb * G * G;
+  HIPCHK(hipMemcpyAsync(x_dev, h->net->x_buf(), sizeof(float) * 3 * pl, hipMemcpyDeviceToDevice, st));
+  if (t_dev) HIPCHK(hipMemcpyAsync(t_dev, h->net->t_buf(), sizeof(float) * pl, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(s_dev, h->net->s_buf(), sizeof(double) * nb, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return PMGRIT_OK;
+}
+
+// counter-based hash (splitmix64 finaliser) for shuffling
+static uint64_t mix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+pmgrit_status pmgrit_net_train(pmgrit_handle* h, const pmgrit_train_opts* opts, const double* const* U_dev,
+                               void* hip_stream, pmgrit_train_stats* stats) {
+  if (!h || !opts || !U_dev || opts->epochs < 0 || opts->batch < 1 || !(opts->lr >= 0.f))
+    return fail(PMGRIT_E_ARG, "bad training arguments");
+  TRY(net_ready(h));
+  if (!h->net->loaded) return fail(PMGRIT_E_STATE, "no network loaded");
+  const int G = h->inst[0].Nin + 2;
+  for (int i = 0; i < h->ninst; ++i) {
+    if (!U_dev[i]) return fail(PMGRIT_E_ARG, "U_dev[i] is NULL");
+    if (h->inst[i].Nin + 2 != G) return fail(PMGRIT_E_ARG, "training needs one grid size for all instances");
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  auto t0 = std::chrono::steady_clock::now();
+  std::vector<NetSrc> src(h->h_netsrc, h->h_netsrc + h->ninst);
+  for (int i = 0; i < h->ninst; ++i) src[i].U = U_dev[i];
+  NetSrc* d_src = nullptr;
+  NetPick* d_pick = nullptr;
+  const int64_t total = (int64_t)h->ninst * h->Nt;
+  HIPCHK(hipMalloc(&d_src, sizeof(NetSrc) * h->ninst));
+  std::unique_ptr<void, void (*)(void*)> g1(d_src, [](void* p) { (void)hipFree(p); });
+  HIPCHK(hipMalloc(&d_pick, sizeof(NetPick) * total));
+  std::unique_ptr<void, void (*)(void*)> g2(d_pick, [](void* p) { (void)hipFree(p); });
+  HIPCHK(hipMemcpy(d_src, src.data(), sizeof(NetSrc) * h->ninst, hipMemcpyHostToDevice));
+  HIPCHK(h->net->reserve(opts->batch, G));
+  pmgrit_train_stats S;
+  std::memset(&S, 0, sizeof(S));
+  std::vector<std::pair<uint64_t, int64_t>> key(total);
+  std::vector<NetPick> order(total);
+  for (int ep = 0; ep < opts->epochs; ++ep) {
+    for (int64_t q = 0; q < total; ++q)
+      key[q] = {mix64(((uint64_t)opts->seed << 40) ^ ((uint64_t)ep << 32) ^ (uint64_t)q), q};
+    std::sort(key.begin(), key.end());
+    for (int64_t q = 0; q < total; ++q)
+      order[q] = {(int)(key[q].second / h->Nt), (int)(key[q].second % h->Nt)};
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(d_pick, order.data(), sizeof(NetPick) * total, hipMemcpyHostToDevice));
+    double lsum = 0.0;
+    int64_t nbat = 0;
+    for (int64_t q0 = 0; q0 < total; q0 += opts->batch) {
+      const int nb = (int)std::min<int64_t>(opts->batch, total - q0);
+      HIPCHK(h->net->train_packed(d_src, d_pick + q0, nb, G, opts->lr, st));
+      double l = 0.0;
+      HIPCHK(h->net->read_loss(&l, st));
+      if (S.adam_steps == 0) S.loss_first = l;
+      ++S.adam_steps;
+      lsum += l;
+      ++nbat;
+    }
+    S.loss_last = nbat ? lsum / nbat : 0.0;
+    S.epochs_done = ep + 1;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = S;
   return PMGRIT_OK;
 }
 

@@ -78,6 +78,9 @@ struct InstDev {
 struct PhiJob {
   int inst, level, k0, len, outj, pad;
 };
+// guess modes of PhiParams::guess: 0 zero, 1 previous point, 2 current target (level 0) /
+// previous point (coarse levels), 4 the better of the current target and the previous point by
+// FP64 residual (level 0; the target then holds a prediction)
 
 enum PhiMode { kModeChain = 0, kModeResidual = 1, kModeGiven = 2 };
 
@@ -94,7 +97,8 @@ struct PhiParams {
   int* status;             // error flags (bit 0 non-finite, bit 1 V-cycle cap)
   double* ws;              // per-workgroup global scratch
   int64_t ws_stride;       // doubles per workgroup
-  int mode, guess, maxcyc, nu1, nu2, pad;
+  int mode, guess, maxcyc, nu1, nu2;
+  int kshift;              // added to every job's first point (one job list serves all steps)
   double stol;
 };
 

@@ -1,6 +1,6 @@
 // phi_kernels.hip -- gfx950 kernels of the spatial solves and the MGRIT point updates.
 //
-// One workgroup (1024 threads, sixteen 64-wide wavefronts) owns one right-hand side and runs the
+// One workgroup (512 threads, eight 64-wide wavefronts) owns one right-hand side and runs the
 // whole spatial solve Phi of Sec. 4 for it: right-hand side M u_k + dt f_{k+1}, FP64 residual,
 // p-multigrid V-cycles (ILUT smoothing, restriction to p = 1, exact p = 1 solve, prolongation)
 // until ||b - A x|| <= tol ||b||, and the MGRIT output (next point, or C-point residual).  A
@@ -487,7 +487,7 @@ __global__ void __launch_bounds__(Cfg<VT>::NT) phi_kernel(PhiParams P, LdsPlan p
   const double stol2 = P.stol * P.stol;
   int total = 0;
   for (int st = 0; st < job.len; ++st) {
-    const int k = job.k0 + st;  // step from point k to point k + 1
+    const int k = job.k0 + P.kshift + st;  // step from point k to point k + 1
     const double* g1 = Gl ? Gl + (int64_t)(k + 1) * n : nullptr;
     double* tgt = Vl ? Vl + (int64_t)(k + 1) * n : nullptr;
     // right-hand side b = M v_k + dt f_{k+1} (level 0) or M v_k, and the initial iterate
@@ -506,9 +506,19 @@ __global__ void __launch_bounds__(Cfg<VT>::NT) phi_kernel(PhiParams P, LdsPlan p
       pass_y<NT, double>(I.nin, I.nin, I.My, yd, 1.0, job.level == 0 ? Fv : (const double*)nullptr, c, false,
                      nullptr, nullptr, b);
       // initial iterate: 0 zero; 1 previous point; 2 current target at level 0 (the previous
-      // MGRIT iterate), previous point at coarse levels (their state restarts from zero)
-      const bool prev = P.guess == 1 || (P.guess == 2 && job.level > 0);
-      for (int i = threadIdx.x; i < n; i += NT) x[i] = prev ? vk[i] : (P.guess == 2 ? tgt[i] : 0.0);
+      // MGRIT iterate), previous point at coarse levels (their state restarts from zero);
+      // 4 at level 0: the current target (there a prediction) or the previous point, whichever
+      // leaves the smaller residual
+      const bool prev = P.guess == 1 || (P.guess >= 2 && job.level > 0);
+      for (int i = threadIdx.x; i < n; i += NT) x[i] = prev ? vk[i] : (P.guess >= 2 ? tgt[i] : 0.0);
+      if (P.guess == 4 && job.level == 0) {
+        __syncthreads();
+        double* rt = sizeof(VT) == 8 ? (double*)r : (double*)(ws + 5 * nm);  // FP64 residual temp
+        const double ra = block_sum<NT>(apply_A<NT, double>(I, L, x, b, rt, yd), red);
+        const double rp = block_sum<NT>(apply_A<NT, double>(I, L, vk, b, rt, yd), red);
+        if (!(ra <= rp))
+          for (int i = threadIdx.x; i < n; i += NT) x[i] = vk[i];
+      }
     }
     __syncthreads();
     double part = 0.0;
