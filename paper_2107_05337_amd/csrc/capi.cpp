@@ -505,19 +505,30 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
   TRY(upload_vals(H, dval, &T.dval));
   if (T.fast) {
     // slot tables: entry 0 reserved (empty slot / zero coefficient whose column is the LDS
-    // zero word); level l, row slot r at 1 + l * R + r; off-block entries padded to AS per row
-    const int R = std::max(1, S.max_rows), AS = RW;
+    // zero word); level l, row slot r at 1 + l * R + r.  Off-block rows: AS = ka * 4 entries in
+    // their natural order, zero-padded.  Dense rows: the columns from bq0 rounded down to 16
+    // bytes (zeros in front) in natural order, zero-padded to a multiple of four 16-byte units;
+    // bc = values per lane.  The kernel's lane g reads 16-byte units g, g + 4, ... of a row.
+    const int R = std::max(1, S.max_rows), AS = RW, TGh = 4;
+    const int V = H->fp32 ? 4 : 2;  // values per 16 bytes
     const size_t nslots = (size_t)(S.nlev + 2) * R + 1;
     std::vector<Meta4> meta(nslots, Meta4{-1, 0, 0, 0});
-    std::vector<int> boff(nslots, 0), acol(aslots, zidx);
+    std::vector<int> acol(aslots, zidx);
     std::vector<double> aval(aslots, 0.0);
+    std::vector<double> dfast((size_t)TGh * V, 0.0);  // a zero row of one vector per lane at 0
+    meta[0] = Meta4{-1, 0, 0, V};
     for (int l = 0; l < S.nlev; ++l)
       for (int q = S.lev_ptr[l]; q < S.lev_ptr[l + 1]; ++q) {
         const int r = q - S.lev_ptr[l];
         const size_t sl = (size_t)l * R + r;
         const int na = S.orp[q + 1] - S.orp[q];
-        meta[1 + sl] = Meta4{S.row[q], na, S.dq0[q], S.dcnt[q]};
-        boff[1 + sl] = (int)(S.doff[q] + 1);
+        const int q0 = S.dq0[q] / V * V, lead = S.dq0[q] - q0, cnt = S.dcnt[q] + lead;
+        const int bc = (cnt + TGh * V - 1) / (TGh * V) * V;
+        const size_t bo = dfast.size();
+        if (bo + (size_t)TGh * bc >= (size_t)INT32_MAX) return fail(PMGRIT_E_OOM, "dense table too large");
+        dfast.resize(bo + (size_t)TGh * bc, 0.0);
+        for (int c = 0; c < S.dcnt[q]; ++c) dfast[bo + lead + c] = S.dval[S.doff[q] + c];
+        meta[1 + sl] = Meta4{S.row[q], (int)bo, q0, bc};
         for (int t = 0; t < na; ++t) {
           aval[(1 + sl) * AS + t] = S.ov[S.orp[q] + t];
           acol[(1 + sl) * AS + t] = S.oci[S.orp[q] + t];
@@ -528,9 +539,8 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
     Meta4* m4;
     TRY(upload_vec(H, meta, &m4));
     T.meta = m4;
+    TRY(upload_vals(H, dfast, &T.dfast));
     int* pi;
-    TRY(upload_vec(H, boff, &pi));
-    T.boff = pi;
     TRY(upload_vec(H, acol, &pi));
     T.acol = pi;
     TRY(upload_vals(H, aval, &T.aval));

@@ -14,7 +14,11 @@ constexpr int kDenseMax = 72;
 
 // per (level, row slot) metadata of the prefetched triangular solve
 struct Meta4 {
-  int row, na, bq0, bcnt;  // row (or -1), off-block count, s position of the dense row, dense count
+  int row;   // row (or -1 for an empty slot)
+  int bo;    // offset of the row's dense chunks in dfast (a multiple of 16 bytes)
+  int bq0;   // s position of the first dense column (a multiple of 16 bytes' worth of values)
+  int bc;    // dense values per lane: the row holds 4 bc values (units of 16 bytes, lane g
+             // reading units g, g + 4, ...)
 };
 
 // level-scheduled blocked triangular solve (see TriSchedule in host_setup.hpp)
@@ -24,7 +28,7 @@ struct TriDev {
   int R, AS, pad0, pad1;         // row slots per level, off-block row width (ka * lanes per row)
   // entry 0 of every table is a reserved zero / empty slot
   const Meta4* meta;             // [1 + (nlev + 2) * R]
-  const int* boff;               // [1 + (nlev + 2) * R] offset of the row's dense entries in dval
+  const void* dfast;             // dense rows, natural column order, 4 * Meta4::bc values each
   const void* aval;              // [(1 + nlev * R) * AS] off-block values, row 0 = padding
   const int* acol;               // [(1 + nlev * R) * AS] off-block columns (padding: the zero word)
   // general path: level-ordered CSR

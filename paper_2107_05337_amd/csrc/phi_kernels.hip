@@ -172,32 +172,68 @@ __device__ double apply_A(const InstDev& I, const LevelDev& L, const XT* x, cons
 template <class T>
 using L3 = __attribute__((address_space(3))) T;
 
+// loads of N values of a row as units of W consecutive values, lane g of the row's quad taking
+// units g, g + 4, g + 8, ...: one instruction reads 4 W contiguous values per row (p must be
+// aligned to W values)
+template <class T, int N, int W>
+__device__ __forceinline__ void qload(const G<T>* p, int g, T* out) {
+  static_assert(N % W == 0, "whole units");
+  if constexpr (W > 1) {
+    typedef T VW __attribute__((ext_vector_type(W)));
+#pragma unroll
+    for (int k = 0; k < N / W; ++k) {
+      const VW v = ((const G<VW>*)p)[k * 4 + g];
+#pragma unroll
+      for (int e = 0; e < W; ++e) out[k * W + e] = v[e];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[k] = p[k * 4 + g];
+  }
+}
+
+// sum over the 4 lanes of a quad with DPP lane permutes (no LDS round trip)
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+template <typename T>
+__device__ __forceinline__ T quad_sum(T v) {
+  v += dpp_mov<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+  v += dpp_mov<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+  return v;
+}
+
 template <typename VT, bool IN_GLOBAL, int KA>
 __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* in_g, L3<VT>* y, L3<VT>* sbuf) {
-  constexpr int NT = Cfg<VT>::NT, TG = Cfg<VT>::TG, TMB = 72 / TG, RW = KA * TG;
+  constexpr int TG = Cfg<VT>::TG, RW = KA * TG, V = 16 / (int)sizeof(VT), BCM = 20;
+  constexpr int WA = KA < V ? KA : V;  // off-block unit width
+  typedef VT VV __attribute__((ext_vector_type(V)));
+  typedef int I4 __attribute__((ext_vector_type(4)));
+  static_assert(TG == 4, "quad sums assume 4 lanes per row");
   const G<VT>* __restrict__ aval = gp((const VT*)Tp->aval);
   const G<int>* __restrict__ acol = gp(Tp->acol);
-  const G<VT>* __restrict__ dv = gp((const VT*)Tp->dval);
-  const G<Meta4>* __restrict__ meta = gp(Tp->meta);
-  const G<int>* __restrict__ boff = gp(Tp->boff);
+  const G<VT>* __restrict__ dv = gp((const VT*)Tp->dfast);
+  const G<I4>* __restrict__ meta = (const G<I4>*)gp(Tp->meta);
   const int R = Tp->R, nlev = Tp->nlev;
   const int r = threadIdx.x / TG, g = threadIdx.x & (TG - 1);
   const bool slot = r < R;
   // wavefronts whose row slots are all empty issue no loads (a wave-uniform branch)
   const bool wave_live = (int)((threadIdx.x & ~63) / TG) < R;
-  auto load_meta = [&](int l, Meta4& m, int& bo) {
+  auto load_meta = [&](int l, Meta4& m) {
     if (!wave_live) {
-      m.row = -1;
-      m.bq0 = 0;
-      m.bcnt = 0;
-      bo = 0;
+      m = Meta4{-1, 0, 0, V};
       return;
     }
-    const int idx = slot ? 1 + l * R + r : 0;
-    m.row = meta[idx].row;
-    m.bq0 = meta[idx].bq0;
-    m.bcnt = meta[idx].bcnt;
-    bo = boff[idx];
+    const I4 v = meta[slot ? 1 + l * R + r : 0];
+    m = Meta4{v.x, v.y, v.z, v.w};
   };
   // off-block rows: a zero row at 0, slot (l, r) at RW + (l * R + r) * RW
   auto load_a = [&](int l, VT* av, int* ac) {
@@ -209,24 +245,25 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* 
       }
       return;
     }
-    const int base = (slot && l < nlev) ? RW + (l * R + r) * RW + g : g;
-#pragma unroll
-    for (int j = 0; j < KA; ++j) {
-      av[j] = aval[base + j * TG];
-      ac[j] = acol[base + j * TG];
-    }
+    const int base = (slot && l < nlev) ? RW + (l * R + r) * RW : 0;
+    qload<VT, KA, WA>(aval + base, g, av);
+    qload<int, KA, WA>(acol + base, g, ac);
   };
-  auto load_b = [&](const Meta4& m, int bo, VT* bv, VT& xin) {
+  // dense row: this lane's units g, g + 4, ... (bc values in all; zeros past them)
+  auto load_b = [&](const Meta4& m, VT* bv, VT& xin) {
     if (!wave_live) {
 #pragma unroll
-      for (int j = 0; j < TMB; ++j) bv[j] = (VT)0;
+      for (int j = 0; j < BCM; ++j) bv[j] = (VT)0;
       xin = (VT)0;
       return;
     }
+    const G<VV>* src = (const G<VV>*)(dv + m.bo);
 #pragma unroll
-    for (int j = 0; j < TMB; ++j) {
-      const int c = g + j * TG;
-      bv[j] = dv[c < m.bcnt ? bo + c : 0];
+    for (int k = 0; k < BCM / V; ++k) {
+      VV v = {};
+      if (k * V < m.bc) v = src[k * 4 + g];
+#pragma unroll
+      for (int e = 0; e < V; ++e) bv[k * V + e] = v[e];
     }
     const int xi = m.row >= 0 ? m.row : 0;
     if constexpr (IN_GLOBAL)
@@ -238,45 +275,49 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* 
     VT s = 0;
 #pragma unroll
     for (int j = 0; j < KA; ++j) s += av[j] * y[ac[j]];
-    s = group_sum<TG>(s);
+    s = quad_sum(s);
     if (g == 0 && row >= 0) sbuf[r] = xin - s;
   };
-  // padding lanes carry zero coefficients; sbuf beyond the level's rows holds finite values
-  auto phase_b = [&](const VT* bv, int row, int bq0) {
+  // padding carries zero coefficients; sbuf beyond the level's rows holds finite values
+  auto phase_b = [&](const VT* bv, const Meta4& m) {
     VT s = 0;
+    const L3<VV>* sp = (const L3<VV>*)(sbuf + m.bq0);
 #pragma unroll
-    for (int j = 0; j < TMB; ++j) s += bv[j] * sbuf[bq0 + g + j * TG];
-    s = group_sum<TG>(s);
-    if (g == 0 && row >= 0) y[row] = s;
+    for (int k = 0; k < BCM / V; ++k) {
+      const VV sv = sp[k * 4 + g];
+#pragma unroll
+      for (int e = 0; e < V; ++e) s += bv[k * V + e] * sv[e];
+    }
+    s = quad_sum(s);
+    if (g == 0 && m.row >= 0) y[m.row] = s;
   };
-  VT av[KA], bv0[TMB], bv1[TMB], x0, x1;
+  VT av[KA], bv0[BCM], bv1[BCM], x0, x1;
   int ac[KA];
   Meta4 M0, M1;
-  int b0, b1;
-  load_meta(0, M0, b0);
-  load_meta(1, M1, b1);
+  load_meta(0, M0);
+  load_meta(1, M1);
   load_a(0, av, ac);
-  load_b(M0, b0, bv0, x0);
+  load_b(M0, bv0, x0);
   for (int l = 0; l < nlev; l += 2) {
     {  // even level l
-      const int row = M0.row, bq = M0.bq0;
-      phase_a(av, ac, row, x0);
+      const Meta4 m = M0;
+      phase_a(av, ac, m.row, x0);
       lds_barrier();
       load_a(l + 1, av, ac);
-      load_b(M1, b1, bv1, x1);
-      load_meta(l + 2, M0, b0);
-      phase_b(bv0, row, bq);
+      load_b(M1, bv1, x1);
+      load_meta(l + 2, M0);
+      phase_b(bv0, m);
       lds_barrier();
     }
     if (l + 1 >= nlev) break;
     {  // odd level l + 1
-      const int row = M1.row, bq = M1.bq0;
-      phase_a(av, ac, row, x1);
+      const Meta4 m = M1;
+      phase_a(av, ac, m.row, x1);
       lds_barrier();
       load_a(l + 2, av, ac);
-      load_b(M0, b0, bv0, x0);
-      load_meta(l + 3, M1, b1);
-      phase_b(bv1, row, bq);
+      load_b(M0, bv0, x0);
+      load_meta(l + 3, M1);
+      phase_b(bv1, m);
       lds_barrier();
     }
   }
