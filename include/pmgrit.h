@@ -78,6 +78,9 @@ typedef struct {
   int32_t coarsest_max; /* stop coarsening at <= this many intervals (e.g. 8) */
   double tol;           /* relative residual, e.g. 1e-10 */
   int32_t max_iter;     /* MGRIT iteration cap */
+  int32_t use_graph;    /* 1: capture one iteration (coarse correction and the next relaxation,
+                         * kernels only) as a HIP graph per set of trajectory buffers and stream,
+                         * and replay it; 0: launch every kernel */
 } pmgrit_mgrit_opts;
 
 /* Spatial solver (Sec. 4).  precision 0: FP64 V-cycle.  precision 1: V-cycle in FP32 as the
@@ -99,6 +102,8 @@ typedef struct {
   int32_t precision;      /* 0 FP64, 1 FP32 V-cycle inside FP64 refinement */
   int32_t guess;          /* 0 zero, 1 previous, 2 current target, 3 learned */
   int32_t trsv_block;     /* see above */
+  int32_t autotune;       /* 1: at create, time candidate LDS placements of the work vectors per
+                           * launch group on probe solves and keep the fastest */
 } pmgrit_solver_opts;
 
 typedef struct {

@@ -32,13 +32,13 @@ class Problem(C.Structure):
 
 class MgritOpts(C.Structure):
     _fields_ = [("cfactor", C.c_int32), ("max_levels", C.c_int32), ("coarsest_max", C.c_int32),
-                ("tol", C.c_double), ("max_iter", C.c_int32)]
+                ("tol", C.c_double), ("max_iter", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class SolverOpts(C.Structure):
     _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("ilut_droptol", C.c_double), ("ilut_fill", C.c_int32),
                 ("spatial_tol", C.c_double), ("max_vcycles", C.c_int32), ("precision", C.c_int32),
-                ("guess", C.c_int32), ("trsv_block", C.c_int32)]
+                ("guess", C.c_int32), ("trsv_block", C.c_int32), ("autotune", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -139,14 +139,14 @@ def _dptr(t):
 
 def default_solver_opts(**kw) -> SolverOpts:
     o = SolverOpts(nu1=1, nu2=1, ilut_droptol=1e-12, ilut_fill=0, spatial_tol=1e-12, max_vcycles=100, precision=0,
-                   guess=2, trsv_block=-1)
+                   guess=2, trsv_block=-1, autotune=0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
 
 
 def default_mgrit_opts(**kw) -> MgritOpts:
-    o = MgritOpts(cfactor=8, max_levels=12, coarsest_max=8, tol=1e-10, max_iter=100)
+    o = MgritOpts(cfactor=8, max_levels=12, coarsest_max=8, tol=1e-10, max_iter=100, use_graph=0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o

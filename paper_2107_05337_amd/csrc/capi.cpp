@@ -106,6 +106,7 @@ struct pmgrit_handle {
   struct Group {
     std::vector<int> inst;
     int mask = 0, lds_bytes = 0, nmax = 0, n1max = 0, ka = 2, rw = 8, maxrows = 1;
+    float tuned_ms = 0.f;  // probe time of the chosen placement (autotune)
     LdsPlan plan{-1, -1, -1, -1, 512, 0, 0, 2};
     std::vector<JobList> jF, jCF, jRES;
     JobList jCoarsest, jSeq;
@@ -143,6 +144,14 @@ struct pmgrit_handle {
   NetSrc* d_src_tmp = nullptr;
   NetPick* d_pick_tmp = nullptr;
   hipEvent_t fork = nullptr;
+  // captured MGRIT iteration (mgrit use_graph) for one set of trajectory buffers and stream
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t gstream = nullptr;  // solve stream of graph mode (the caller's may be the null stream)
+  hipEvent_t gfork = nullptr, gjoin = nullptr;
+  std::vector<void*> graph_key;
+  hipStream_t graph_stream = nullptr;
+  int64_t graph_phi = 0, graph_launches = 0, graph_wgs = 0;
+  int64_t nlaunch_total = 0, nwg_total = 0;  // spatial-solve launches issued or captured
   // live kernel timing
   bool prof = false;
   std::vector<hipEvent_t> ev;
@@ -621,6 +630,19 @@ static void lds_plan(int nmax, int n1max, int maxrows, int vt, int ka, int dev_l
   }
 }
 
+// LDS plan with exactly the vectors of `mask` in LDS (bytes = 0 when it does not fit)
+static LdsPlan lds_plan_mask(int nmax, int n1max, int maxrows, int vt, int ka, int dev_lds, int mask, int& bytes) {
+  auto al = [](int b) { return (b + 15) / 16 * 16; };
+  int off = 512 + al(std::max(maxrows, 256) * vt);
+  LdsPlan plan{-1, -1, -1, -1, 512, nmax, nmax * 8 / vt, ka};
+  if (mask & kY) { plan.off_y = off; off += al(nmax * 8 + 16); }
+  if (mask & kD) { plan.off_d = off; off += al(nmax * vt); }
+  if (mask & kS) { plan.off_s = off; off += al(std::max(nmax * vt, n1max * 8)); }
+  if (mask & kX) { plan.off_x = off; off += al(nmax * 8); }
+  bytes = off <= dev_lds ? off : 0;
+  return plan;
+}
+
 static int inst_maxrows(const InstHost& I) {
   int r = 1;
   for (const LevelHost& Lh : I.lev) r = std::max(r, std::max(Lh.SL.max_rows, Lh.SU.max_rows));
@@ -870,6 +892,9 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
   }
   TRY(learned_setup(H));
   HIPCHK(hipEventCreateWithFlags(&H->fork, hipEventDisableTiming));
+  HIPCHK(hipStreamCreateWithFlags(&H->gstream, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&H->gfork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&H->gjoin, hipEventDisableTiming));
   TRY(upload<int>(H, nullptr, 4, &H->d_status));
   TRY(upload<double>(H, nullptr, (size_t)H->ninst, &H->d_resnorm));
   HIPCHK(hipMemset(H->d_status, 0, sizeof(int) * 4));
@@ -920,6 +945,8 @@ static hipError_t harvest(pmgrit_handle* H) {
 
 static hipError_t phi_timed(pmgrit_handle* H, const pmgrit_handle::Group& G, const PhiParams& P, int nblocks,
                             hipStream_t st) {
+  H->nlaunch_total++;
+  H->nwg_total += nblocks;
   if (!H->prof) return phi_launch(H->fp32, G.mask, G.lds_bytes, P, G.plan, nblocks, st);
   hipError_t e;
   if (H->ev_used * 2 + 2 > (int)H->ev.size()) {
@@ -1061,6 +1088,87 @@ static int64_t sum_vcycles(pmgrit_handle* H, hipStream_t st) {
   return s;
 }
 
+// Autotuner: for every launch group, time probe solves (level 0 of its first instance, one
+// right-hand side per workgroup slot of a level-0 sweep, up to the pmgrit_phi limit) with each LDS
+// placement that keeps the triangular-solve vector in LDS, and keep the fastest.  The
+// placements differ only in where vectors live, so the arithmetic and the results are the same.
+static pmgrit_status autotune(pmgrit_handle* H) {
+  HIPCHK(hipSetDevice(H->device));
+  const int vt = H->fp32 ? 4 : 8;
+  int dev_lds = 0;
+  HIPCHK(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, H->device));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (pmgrit_handle::Group& G : H->groups) {
+    if (!(G.mask & kY)) continue;  // placements without y in LDS use the general solve
+    const int inst = G.inst[0];
+    const int nd = H->inst[inst].ndof;
+    const int nrhs = std::max(1, std::min(kGivenMax, G.jF.empty() ? 64 : std::max(G.jF[0].n, 64)));
+    std::vector<double> hb((size_t)nrhs * nd);
+    uint64_t z = 0x2545F4914F6CDD1Dull;
+    for (double& v : hb) {  // a fixed pseudo-random right-hand side (xorshift64)
+      z ^= z << 13;
+      z ^= z >> 7;
+      z ^= z << 17;
+      v = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    }
+    double *b = nullptr, *x = nullptr;
+    HIPCHK(hipMalloc(&b, sizeof(double) * hb.size()));
+    std::unique_ptr<void, void (*)(void*)> gb(b, [](void* p) { (void)hipFree(p); });
+    HIPCHK(hipMalloc(&x, sizeof(double) * hb.size()));
+    std::unique_ptr<void, void (*)(void*)> gx(x, [](void* p) { (void)hipFree(p); });
+    HIPCHK(hipMemcpy(b, hb.data(), sizeof(double) * hb.size(), hipMemcpyHostToDevice));
+    for (int j = 0; j < nrhs; ++j) H->h_given_jobs[j] = PhiJob{inst, 0, 0, 1, 0, 0};
+    HIPCHK(hipMemcpy(G.d_given_jobs, H->h_given_jobs, sizeof(PhiJob) * nrhs, hipMemcpyHostToDevice));
+    H->given_key[0] = -1;
+    const int keep_mask = G.mask, keep_bytes = G.lds_bytes;
+    const LdsPlan keep_plan = G.plan;
+    int best_mask = keep_mask, best_bytes = keep_bytes;
+    LdsPlan best_plan = keep_plan;
+    float best_ms = 1e30f;
+    for (int mk : {15, 7, 3, 1}) {
+      int bytes = 0;
+      const LdsPlan plan = lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, G.ka, dev_lds, mk, bytes);
+      if (bytes == 0) continue;
+      HIPCHK(phi_prepare(H->fp32, mk, bytes));
+      G.mask = mk;
+      G.lds_bytes = bytes;
+      G.plan = plan;
+      PhiParams P = base_params(H, G, kModeGiven, G.d_given_jobs);
+      P.vtab = nullptr;
+      P.bgiven = b;
+      P.xgiven = x;
+      P.guess = 0;
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        HIPCHK(hipMemset(x, 0, sizeof(double) * hb.size()));
+        HIPCHK(hipEventRecord(e0, nullptr));
+        HIPCHK(phi_launch(H->fp32, mk, bytes, P, plan, nrhs, nullptr));
+        HIPCHK(hipEventRecord(e1, nullptr));
+        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_mask = mk;
+        best_bytes = bytes;
+        best_plan = plan;
+      }
+    }
+    G.mask = best_mask;
+    G.lds_bytes = best_bytes;
+    G.plan = best_plan;
+    G.tuned_ms = best_ms;
+    HIPCHK(phi_prepare(H->fp32, G.mask, G.lds_bytes));
+  }
+  HIPCHK(hipEventDestroy(e0));
+  HIPCHK(hipEventDestroy(e1));
+  HIPCHK(hipMemset(H->d_status, 0, sizeof(int) * 4));
+  for (pmgrit_handle::Group& G : H->groups) HIPCHK(hipMemset(G.d_vcount, 0, sizeof(int) * G.max_jobs));
+  return PMGRIT_OK;
+}
+
 extern "C" {
 
 const char* pmgrit_last_error(void) { return g_err.c_str(); }
@@ -1072,10 +1180,11 @@ pmgrit_status pmgrit_create(int32_t n_instances, const pmgrit_problem* probs, co
   const pmgrit_mgrit_opts& mo = *mopts;
   const pmgrit_solver_opts& so = *sopts;
   if (mo.cfactor < 2 || mo.max_levels < 1 || mo.max_levels > kMaxLevels || mo.coarsest_max < 1 || mo.max_iter < 0 ||
-      !(mo.tol >= 0))
+      !(mo.tol >= 0) || mo.use_graph < 0 || mo.use_graph > 1)
     return fail(PMGRIT_E_ARG, "invalid MGRIT options");
   if (so.nu1 < 1 || so.nu2 < 0 || !(so.ilut_droptol >= 0) || !(so.spatial_tol > 0) || so.max_vcycles < 1 ||
-      (so.precision != 0 && so.precision != 1) || so.guess < 0 || so.guess > 3 || so.trsv_block < -1)
+      (so.precision != 0 && so.precision != 1) || so.guess < 0 || so.guess > 3 || so.trsv_block < -1 ||
+      so.autotune < 0 || so.autotune > 1)
     return fail(PMGRIT_E_ARG, "invalid solver options");
   for (int i = 0; i < n_instances; ++i) {
     const pmgrit_problem& p = probs[i];
@@ -1115,6 +1224,7 @@ pmgrit_status pmgrit_create(int32_t n_instances, const pmgrit_problem* probs, co
   }
   if (hip_device >= 0) {
     pmgrit_status s = device_setup(H.get());
+    if (s == PMGRIT_OK && H->so.autotune) s = autotune(H.get());
     if (s != PMGRIT_OK) {
       std::string keep = g_err;
       pmgrit_destroy(H.release());
@@ -1136,6 +1246,10 @@ void pmgrit_destroy(pmgrit_handle* h) {
     if (h->h_pinned) (void)hipHostFree(h->h_pinned);
     if (h->h_given_jobs) (void)hipHostFree(h->h_given_jobs);
     if (h->h_netsrc) (void)hipHostFree(h->h_netsrc);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->gstream) (void)hipStreamDestroy(h->gstream);
+    if (h->gfork) (void)hipEventDestroy(h->gfork);
+    if (h->gjoin) (void)hipEventDestroy(h->gjoin);
     h->net.reset();
     for (hipEvent_t e : h->ev)
       if (e) (void)hipEventDestroy(e);
@@ -1240,6 +1354,121 @@ pmgrit_status pmgrit_set_initial_coeffs(pmgrit_handle* h, int32_t inst, const do
   return PMGRIT_OK;
 }
 
+// level-0 F-relaxation, C-relaxation with the following F-relaxation, C-point residuals and their
+// norms per instance (into d_resnorm)
+static hipError_t relax_level0(pmgrit_handle* h, hipStream_t st, bool learned, int64_t& phi) {
+  hipError_t e;
+  if (learned) {
+    // learned guesses: the same relaxations one step position at a time, each preceded by the
+    // network's predictions for its targets
+    auto fsplit = [&]() -> hipError_t {
+      for (int s = 0; s + 1 < h->m; ++s) {
+        hipError_t e2 = net_predict(h, 1, s, 0, st);
+        if (e2 == hipSuccess)
+          e2 = sweep(h, [s](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF1[s]; }, kModeChain, st,
+                     4);
+        if (e2 != hipSuccess) return e2;
+      }
+      return hipSuccess;
+    };
+    if ((e = fsplit()) != hipSuccess) return e;
+    if ((e = net_predict(h, 2, 0, 0, st)) != hipSuccess) return e;
+    if ((e = sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jC1; }, kModeChain, st, 4)) !=
+        hipSuccess)
+      return e;
+    if ((e = fsplit()) != hipSuccess) return e;
+  } else {
+    if ((e = sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF[0]; }, kModeChain, st)) !=
+        hipSuccess)
+      return e;
+    if ((e = sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jCF[0]; }, kModeChain, st)) !=
+        hipSuccess)
+      return e;
+  }
+  if ((e = sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jRES[0]; }, kModeResidual,
+                 st)) != hipSuccess)
+    return e;
+  for (pmgrit_handle::Group& G : h->groups)
+    if ((e = norm_reduce_launch(G.d_nrm2, G.d_res_begin, G.d_res_inst, h->d_resnorm, (int)G.inst.size(), st)) !=
+        hipSuccess)
+      return e;
+  phi += 2 * sweep_steps(h, 0, 0) + sweep_steps(h, 1, 0) + sweep_steps(h, 2, 0);
+  return hipSuccess;
+}
+
+// coarse-grid correction of level 0: solve the level-1 correction equation by a recursive cycle
+// and add it to the level-0 C-points
+static hipError_t correct_level0(pmgrit_handle* h, hipStream_t st, double* const* u_out, int64_t& phi) {
+  hipError_t e;
+  for (int i = 0; i < h->ninst; ++i) {
+    double* vc = h->h_vtab[(size_t)i * kMaxLevels + 1];
+    if ((e = fill_launch(vc, (int64_t)(h->Nl[1] + 1) * h->inst[i].ndof, 0.0, st)) != hipSuccess) return e;
+  }
+  if ((e = coarse_cycle(h, 1, st, phi)) != hipSuccess) return e;
+  for (int i = 0; i < h->ninst; ++i) {
+    double* vc = h->h_vtab[(size_t)i * kMaxLevels + 1];
+    if ((e = correct_launch(u_out[i], vc, h->inst[i].ndof, h->m, h->Nl[1], st)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// one MGRIT iteration after the first (correction, then the next relaxation) captured as a HIP
+// graph for the given trajectory buffers; the kernels only (no memset or copy nodes)
+static pmgrit_status capture_iteration(pmgrit_handle* h, hipStream_t st, double* const* u_out) {
+  std::vector<void*> key(u_out, u_out + h->ninst);
+  if (h->graph_exec && key == h->graph_key && h->graph_stream == st) return PMGRIT_OK;
+  if (h->graph_exec) {
+    HIPCHK(hipGraphExecDestroy(h->graph_exec));
+    h->graph_exec = nullptr;
+  }
+  const bool prof = h->prof;
+  h->prof = false;  // no timing events inside the graph
+  hipGraph_t g = nullptr;
+  int64_t phi = 0;
+  const int64_t nl0 = h->nlaunch_total, nw0 = h->nwg_total;
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t eb = correct_level0(h, st, u_out, phi);
+    if (eb == hipSuccess) eb = relax_level0(h, st, false, phi);
+    e = hipStreamEndCapture(st, &g);
+    if (eb != hipSuccess) e = eb;
+  }
+  h->prof = prof;
+  if (e == hipSuccess) e = hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->graph_exec = nullptr;
+    return fail(PMGRIT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  h->graph_key = key;
+  h->graph_stream = st;
+  h->graph_phi = phi;
+  h->graph_launches = h->nlaunch_total - nl0;
+  h->graph_wgs = h->nwg_total - nw0;
+  h->nlaunch_total = nl0;
+  h->nwg_total = nw0;
+  return PMGRIT_OK;
+}
+
+// replay of the captured iteration; with timing on, one event pair brackets the whole graph (its
+// spatial-solve launches are counted, the small kernels between them are included in the time)
+static hipError_t graph_launch_timed(pmgrit_handle* h, hipStream_t st) {
+  h->nlaunch_total += h->graph_launches;
+  h->nwg_total += h->graph_wgs;
+  if (!h->prof) return hipGraphLaunch(h->graph_exec, st);
+  hipError_t e;
+  if (h->ev_used * 2 + 2 > (int)h->ev.size()) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+    if ((e = harvest(h)) != hipSuccess) return e;
+  }
+  const int k = h->ev_used++;
+  if ((e = hipEventRecord(h->ev[2 * k], st)) != hipSuccess) return e;
+  if ((e = hipGraphLaunch(h->graph_exec, st)) != hipSuccess) return e;
+  h->prof_launches += h->graph_launches;
+  h->prof_wgs += h->graph_wgs;
+  return hipEventRecord(h->ev[2 * k + 1], st);
+}
+
 pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* const* u_out_dev, pmgrit_stats* stats) {
   if (!h) return fail(PMGRIT_E_ARG, "null handle");
   hipStream_t st = (hipStream_t)hip_stream;
@@ -1251,43 +1480,29 @@ pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* con
   int64_t phi = 0;
   int iters = 0;
   pmgrit_status rc = PMGRIT_OK;
+  hipStream_t caller = nullptr;
+  bool forked = false;
   auto seq = [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jSeq; };
   if (h->nlev == 1) {
     HIPCHK(sweep(h, seq, kModeChain, st, h->so.guess == 0 ? 0 : 1));
     phi += sweep_steps(h, 4, 0);
   } else {
+    const bool graph = h->mo.use_graph != 0;
+    if (graph) {
+      // the whole solve runs on the library's own stream, ordered after the caller's work
+      HIPCHK(hipEventRecord(h->gfork, st));
+      HIPCHK(hipStreamWaitEvent(h->gstream, h->gfork, 0));
+      caller = st;
+      st = h->gstream;
+      forked = true;
+      TRY(capture_iteration(h, st, u_out_dev));
+    }
     std::vector<double> r0(h->ninst, -1.0);
+    HIPCHK(relax_level0(h, st, h->so.guess == 3, phi));
     for (;;) {
-      // level-0 F-relaxation, C-relaxation with the following F-relaxation, residual at C-points
-      if (h->so.guess == 3 && iters == 0) {
-        // first iteration with learned guesses: the same relaxations one step position at a
-        // time, each preceded by the network's predictions for its targets
-        auto fsplit = [&]() -> hipError_t {
-          for (int s = 0; s + 1 < h->m; ++s) {
-            hipError_t e = net_predict(h, 1, s, 0, st);
-            if (e == hipSuccess)
-              e = sweep(h, [s](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF1[s]; }, kModeChain,
-                        st, 4);
-            if (e != hipSuccess) return e;
-          }
-          return hipSuccess;
-        };
-        HIPCHK(fsplit());
-        HIPCHK(net_predict(h, 2, 0, 0, st));
-        HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jC1; }, kModeChain, st, 4));
-        HIPCHK(fsplit());
-      } else {
-        HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF[0]; }, kModeChain, st));
-        HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jCF[0]; }, kModeChain, st));
-      }
-      HIPCHK(sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jRES[0]; }, kModeResidual,
-                   st));
-      for (pmgrit_handle::Group& G : h->groups)
-        HIPCHK(norm_reduce_launch(G.d_nrm2, G.d_res_begin, G.d_res_inst, h->d_resnorm, (int)G.inst.size(), st));
       HIPCHK(hipMemcpyAsync(h->h_pinned, h->d_resnorm, sizeof(double) * h->ninst, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       HIPCHK(harvest(h));
-      phi += 2 * sweep_steps(h, 0, 0) + sweep_steps(h, 1, 0) + sweep_steps(h, 2, 0);
       bool done = true, bad = false;
       double worst = 0.0;
       for (int i = 0; i < h->ninst; ++i) {
@@ -1313,19 +1528,21 @@ pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* con
         rc = fail(PMGRIT_E_MGRIT_NOCONV, "MGRIT reached max_iter");
         break;
       }
-      for (int i = 0; i < h->ninst; ++i) {
-        double* vc = h->h_vtab[(size_t)i * kMaxLevels + 1];
-        HIPCHK(fill_launch(vc, (int64_t)(h->Nl[1] + 1) * h->inst[i].ndof, 0.0, st));
-      }
-      HIPCHK(coarse_cycle(h, 1, st, phi));
-      for (int i = 0; i < h->ninst; ++i) {
-        double* vc = h->h_vtab[(size_t)i * kMaxLevels + 1];
-        HIPCHK(correct_launch(u_out_dev[i], vc, h->inst[i].ndof, h->m, h->Nl[1], st));
+      if (graph) {
+        HIPCHK(graph_launch_timed(h, st));
+        phi += h->graph_phi;
+      } else {
+        HIPCHK(correct_level0(h, st, u_out_dev, phi));
+        HIPCHK(relax_level0(h, st, false, phi));
       }
       ++iters;
     }
   }
   HIPCHK(hipStreamSynchronize(st));
+  if (forked) {
+    HIPCHK(hipEventRecord(h->gjoin, st));
+    HIPCHK(hipStreamWaitEvent(caller, h->gjoin, 0));
+  }
   HIPCHK(harvest(h));
   if (rc == PMGRIT_OK) rc = read_status(h, st);
   S.mgrit_iters = iters;

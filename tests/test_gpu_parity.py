@@ -34,12 +34,13 @@ def torch():
     return T
 
 
-def make_solver(cfg, precision=0, guess=2, trsv_block=-1, tol=1e-10, stol=1e-12, **mo):
+def make_solver(cfg, precision=0, guess=2, trsv_block=-1, tol=1e-10, stol=1e-12, autotune=0, **mo):
     probs = [pm.problem(d["p"], d["n"], d["Nt"], kappa=d["kappa"], T=d["T"], domain=d["domain"])
              for d in cfg["instances"]]
     mopts = pm.default_mgrit_opts(cfactor=cfg["m"], max_levels=cfg["max_levels"], coarsest_max=cfg["coarsest_max"],
                                   tol=tol, **mo)
-    sopts = pm.default_solver_opts(precision=precision, guess=guess, trsv_block=trsv_block, spatial_tol=stol)
+    sopts = pm.default_solver_opts(precision=precision, guess=guess, trsv_block=trsv_block, spatial_tol=stol,
+                                   autotune=autotune)
     S = pm.Solver(probs, mopts, sopts, device=0)
     for i, d in enumerate(cfg["instances"]):
         S.set_source(i, d["src"], d["tkind"])
@@ -185,3 +186,55 @@ def test_deterministic(torch):
     (U1,), _ = S.solve_mgrit()
     (U2,), _ = S.solve_mgrit()
     assert torch.equal(U1, U2)
+
+
+@pytest.mark.parametrize("hetero", [False, True])
+def test_graph_replay_matches_eager(torch, hetero):
+    """The captured MGRIT iteration (kernels only) replayed every iteration gives bitwise the eager
+    result, also on a second solve that replays the cached graph after unrelated eager work."""
+    if hetero:  # two launch groups: the capture contains the fork / join across group streams
+        insts = [dict(p=2, n=8, domain=0, kappa=1.0, T=0.1, Nt=128, src=W.random_modes(21, 3, 4), tkind=0, init=[]),
+                 dict(p=4, n=128, domain=1, kappa=0.5, T=0.1, Nt=128, src=W.random_modes(22, 3, 4), tkind=0,
+                      init=[])]
+        cfg = dict(instances=insts, m=4, max_levels=4, coarsest_max=4)
+    else:
+        cfg = W.small("x", 3, 16, 256)
+        cfg["m"], cfg["max_levels"], cfg["coarsest_max"] = 4, 4, 4
+    say(f"case graph replay hetero={hetero}")
+    Se = make_solver(cfg, tol=1e-12)
+    Ue, ste = Se.solve_mgrit()
+    Sg = make_solver(cfg, tol=1e-12, use_graph=1)
+    if hetero:
+        assert Sg.group_info(0)["groups"] == 2
+    outs = Sg.alloc_trajectories()
+    Ug, stg = Sg.solve_mgrit(outs)
+    first = [u.clone() for u in Ug]
+    junk = torch.randn(1 << 20, device="cuda")
+    junk = (junk * 2).sum()  # eager work between the solves
+    torch.cuda.synchronize()
+    Ug2, stg2 = Sg.solve_mgrit(outs)
+    say(f"  iters eager {ste['mgrit_iters']} graph {stg['mgrit_iters']} / {stg2['mgrit_iters']}")
+    assert ste["mgrit_iters"] == stg["mgrit_iters"] == stg2["mgrit_iters"] >= 2
+    assert ste["phi_calls"] == stg["phi_calls"] and ste["vcycles"] == stg["vcycles"]
+    for a, b, c in zip(Ue, first, Ug2):
+        assert torch.equal(a, b) and torch.equal(a, c)
+    for i, d in enumerate(cfg["instances"]):
+        assert rel(first[i].cpu().numpy(), oracle_sequential(d)) <= EPS
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_autotune_same_result(torch, precision):
+    """The autotuner only moves work vectors between LDS and global scratch: same results."""
+    name = "heat-p3-h64-Nt1024"
+    cfg = W.config(name)
+    cfg["instances"][0]["Nt"] = 128
+    cfg["instances"][0]["T"] = 0.1 / 8
+    say(f"case autotune precision={precision}")
+    S0 = make_solver(cfg, precision=precision)
+    (U0,), st0 = S0.solve_mgrit()
+    S1 = make_solver(cfg, precision=precision, autotune=1)
+    gi = S1.group_info(0)
+    say(f"  default {S0.group_info(0)['lds_mask']} tuned {gi['lds_mask']} ({gi['lds_bytes']} B)")
+    (U1,), st1 = S1.solve_mgrit()
+    assert gi["lds_mask"] & 1
+    assert torch.equal(U0, U1) and st0["vcycles"] == st1["vcycles"]
