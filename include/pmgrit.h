@@ -104,6 +104,9 @@ typedef struct {
   int32_t trsv_block;     /* see above */
   int32_t autotune;       /* 1: at create, time candidate LDS placements of the work vectors per
                            * launch group on probe solves and keep the fastest */
+  double coarse_tol;      /* spatial tolerance of the solves on MGRIT levels >= 1 (0: spatial_tol);
+                           * those only supply corrections, so it changes the convergence rate,
+                           * not the fixed point that the level-0 stop test measures */
 } pmgrit_solver_opts;
 
 typedef struct {
@@ -244,8 +247,8 @@ typedef struct {
 } pmgrit_train_stats;
 
 /* Train the handle's network (from its loaded parameters) on the level-0 steps of trajectories the
- * solver produced: U_dev[i] is instance i's (N_t + 1) x n_dof trajectory (device).  Every instance
- * must have the same grid size G.  Synchronous. */
+ * solver produced: U_dev[i] is instance i's (N_t + 1) x n_dof trajectory (device).  A batch holds
+ * samples of one grid size; with several grid sizes their batches alternate.  Synchronous. */
 pmgrit_status pmgrit_net_train(pmgrit_handle* h, const pmgrit_train_opts* opts, const double* const* U_dev,
                                void* hip_stream, pmgrit_train_stats* stats);
 

@@ -71,7 +71,7 @@ def lib():
                                          C.c_double, C.c_double, C.c_int, _dp, _llp]
         L.orc_mgrit.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, _dp, C.c_int, _dp,
                                 C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, C.c_double,
-                                C.c_int, C.c_int, _dp, _ip, _llp, _llp, _dp]
+                                C.c_double, C.c_int, C.c_int, _dp, _ip, _llp, _llp, _dp]
         _lib = L
     return _lib
 
@@ -248,8 +248,9 @@ class Problem:
         return rc, U, cyc.value
 
     def mgrit(self, kappa, T, Nt, F, tkind, u0, m=8, max_levels=30, coarsest_max=8, tol=1e-10,
-              max_iter=100, tau=1e-12, stol=1e-12, maxcyc=100, guess=2):
-        """MGRIT with p-multigrid spatial solves.  Returns dict(rc, U, iters, cycles, solves, hist)."""
+              max_iter=100, tau=1e-12, stol=1e-12, maxcyc=100, guess=2, ctol=0.0):
+        """MGRIT with p-multigrid spatial solves (level-0 tolerance stol, coarse levels ctol, 0 = stol).
+        Returns dict(rc, U, iters, cycles, solves, hist)."""
         F = np.ascontiguousarray(F, dtype=np.float64)
         u0 = np.ascontiguousarray(u0, dtype=np.float64)
         U = np.zeros((Nt + 1, self.ndof))
@@ -258,7 +259,7 @@ class Problem:
         sol = C.c_longlong(0)
         hist = np.zeros(200)
         rc = lib().orc_mgrit(self._h, kappa, T, Nt, _d(F), tkind, _d(u0), m, max_levels, coarsest_max,
-                             tol, max_iter, tau, stol, maxcyc, guess, _d(U), C.byref(it), C.byref(cyc),
+                             tol, max_iter, tau, stol, ctol, maxcyc, guess, _d(U), C.byref(it), C.byref(cyc),
                              C.byref(sol), _d(hist))
         return dict(rc=rc, U=U, iters=it.value, cycles=cyc.value, solves=sol.value,
                     hist=hist[: it.value + 1].copy())

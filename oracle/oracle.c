@@ -1279,11 +1279,14 @@ static double mgrit_cycle(omgrit *S, int l, int do_interp) {
  * Stop when ||r^{(k)}|| <= tol ||r^{(0)}|| with r the level-0 C-point residual after
  * FCF-relaxation (reading of the relative residual criterion of Sec. 5).  The converged
  * iterate is the post-FCF state, whose F-points are already consistent.
+ * Spatial solves stop at stol on level 0 and at ctol on the coarse levels (ctol <= 0: stol).
+ * The paper fixes neither; the coarse levels only supply corrections, so their tolerance
+ * changes the convergence rate, not the fixed point that the level-0 test measures.
  * out: iters, V-cycles, spatial solves; res_hist (up to 200 entries, relative). */
 ORC_API int orc_mgrit(const oprob *P, double kappa, double T, int Nt, const double *F, int tkind, const double *u0,
                       int m, int max_levels, int coarsest_max, double tol, int max_iter, double tau, double stol,
-                      int maxcyc, int guess, double *U, int *iters, long long *cycles, long long *solves,
-                      double *res_hist) {
+                      double ctol, int maxcyc, int guess, double *U, int *iters, long long *cycles,
+                      long long *solves, double *res_hist) {
   int n = P->ndof;
   omgrit S;
   memset(&S, 0, sizeof(S));
@@ -1311,7 +1314,7 @@ ORC_API int orc_mgrit(const oprob *P, double kappa, double T, int Nt, const doub
   for (int l = 0; l < nlev; ++l) {
     S.L[l].Nl = Nl;
     S.L[l].dt = dt;
-    if (rc == 0) rc = pmg_init(&S.L[l].G, P, kappa, dt, tau, 1, 1, stol, maxcyc);
+    if (rc == 0) rc = pmg_init(&S.L[l].G, P, kappa, dt, tau, 1, 1, (l > 0 && ctol > 0) ? ctol : stol, maxcyc);
     S.L[l].v = l == 0 ? U : (double *)xcalloc((size_t)(Nl + 1) * n, sizeof(double));
     S.L[l].g = l == 0 ? NULL : (double *)xcalloc((size_t)(Nl + 1) * n, sizeof(double));
     Nl /= m;

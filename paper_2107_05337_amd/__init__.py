@@ -38,7 +38,8 @@ class MgritOpts(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("ilut_droptol", C.c_double), ("ilut_fill", C.c_int32),
                 ("spatial_tol", C.c_double), ("max_vcycles", C.c_int32), ("precision", C.c_int32),
-                ("guess", C.c_int32), ("trsv_block", C.c_int32), ("autotune", C.c_int32)]
+                ("guess", C.c_int32), ("trsv_block", C.c_int32), ("autotune", C.c_int32),
+                ("coarse_tol", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -139,7 +140,7 @@ def _dptr(t):
 
 def default_solver_opts(**kw) -> SolverOpts:
     o = SolverOpts(nu1=1, nu2=1, ilut_droptol=1e-12, ilut_fill=0, spatial_tol=1e-12, max_vcycles=100, precision=0,
-                   guess=2, trsv_block=-1, autotune=0)
+                   guess=2, trsv_block=-1, autotune=0, coarse_tol=0.0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o

@@ -108,12 +108,12 @@ struct pmgrit_handle {
     int mask = 0, lds_bytes = 0, nmax = 0, n1max = 0, ka = 2, rw = 8, maxrows = 1;
     float tuned_ms = 0.f;  // probe time of the chosen placement (autotune)
     LdsPlan plan{-1, -1, -1, -1, 512, 0, 0, 2};
-    std::vector<JobList> jF, jCF, jRES;
+    std::vector<JobList> jF, jC, jRES;  // per level: F-relaxation chains, C-steps, C-point residuals
     JobList jCoarsest, jSeq;
     // single-step lists of the learned warm start: level-0 F steps per position s in the
-    // interval, level-0 C steps, and one step per instance (sequential stepping, shifted by k)
+    // interval, and one step per instance (sequential stepping, shifted by k)
     std::vector<JobList> jF1;
-    JobList jC1, jSeq1;
+    JobList jSeq1;
     int max_jobs = 0;
     double* d_ws = nullptr;
     int64_t ws_stride = 0;
@@ -691,12 +691,8 @@ static pmgrit_status learned_setup(pmgrit_handle* H) {
       for (int i : G.inst) fsteps(i, s, [&](int ii, int k) { J.push_back({ii, 0, k, 1, 0, 0}); });
       TRY(upload_jobs(H, G, J, G.jF1[s]));
     }
-    std::vector<PhiJob> C, S1;
-    for (int i : G.inst) {
-      csteps(i, [&](int ii, int k) { C.push_back({ii, 0, k, 1, 0, 0}); });
-      S1.push_back({i, 0, 0, 1, 0, 0});
-    }
-    TRY(upload_jobs(H, G, C, G.jC1));
+    std::vector<PhiJob> S1;
+    for (int i : G.inst) S1.push_back({i, 0, 0, 1, 0, 0});
     TRY(upload_jobs(H, G, S1, G.jSeq1));
   }
   // network batches: instances of one grid size
@@ -846,26 +842,28 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
   const int m = H->m;
   for (pmgrit_handle::Group& G : H->groups) {
     G.jF.resize(H->nlev);
-    G.jCF.resize(H->nlev);
+    G.jC.resize(H->nlev);
     G.jRES.resize(H->nlev);
     std::vector<int> res_begin(1, 0);
     for (int l = 0; l + 1 < H->nlev; ++l) {
-      std::vector<PhiJob> F, CF, RES;
+      // C-relaxation reads the F-points of the preceding F-relaxation, so it is a launch of its
+      // own: a fused C-and-F chain would race with the chain of the previous interval, which
+      // rewrites the F-point the C-step reads
+      std::vector<PhiJob> F, C, RES;
       const int Nl = H->Nl[l];
       for (int i : G.inst) {
         for (int j = 0; j * m < Nl; ++j) {
           int len = std::min(m - 1, Nl - j * m);
           if (len > 0) F.push_back({i, l, j * m, len, 0, 0});
-          if (j == 0 && len > 0) CF.push_back({i, l, 0, len, 0, 0});
         }
         for (int j = 1; j * m <= Nl; ++j) {
-          CF.push_back({i, l, j * m - 1, std::min(m, Nl - j * m + 1), 0, 0});
+          C.push_back({i, l, j * m - 1, 1, 0, 0});
           RES.push_back({i, l, j * m - 1, 1, j, 0});
         }
         if (l == 0) res_begin.push_back((int)RES.size());
       }
       TRY(upload_jobs(H, G, F, G.jF[l]));
-      TRY(upload_jobs(H, G, CF, G.jCF[l]));
+      TRY(upload_jobs(H, G, C, G.jC[l]));
       TRY(upload_jobs(H, G, RES, G.jRES[l]));
     }
     std::vector<PhiJob> C, S;
@@ -928,6 +926,7 @@ static PhiParams base_params(pmgrit_handle* H, const pmgrit_handle::Group& G, in
   P.nu1 = H->so.nu1;
   P.nu2 = H->so.nu2;
   P.stol = H->so.spatial_tol;
+  P.stolc = H->so.coarse_tol > 0 ? H->so.coarse_tol : H->so.spatial_tol;
   return P;
 }
 
@@ -991,7 +990,7 @@ static hipError_t sweep(pmgrit_handle* H, Pick pick, int mode, hipStream_t st, i
 static int64_t sweep_steps(pmgrit_handle* H, int kind, int l) {
   int64_t s = 0;
   for (pmgrit_handle::Group& G : H->groups)
-    s += kind == 0 ? G.jF[l].steps : kind == 1 ? G.jCF[l].steps : kind == 2 ? G.jRES[l].steps
+    s += kind == 0 ? G.jF[l].steps : kind == 1 ? G.jC[l].steps : kind == 2 ? G.jRES[l].steps
                                                                           : kind == 3 ? G.jCoarsest.steps : G.jSeq.steps;
   return s;
 }
@@ -1016,16 +1015,18 @@ static hipError_t coarse_cycle(pmgrit_handle* H, int l, hipStream_t st, int64_t&
     phi += sweep_steps(H, 3, l);
     return sweep(H, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jCoarsest; }, kModeChain, st);
   }
-  if ((e = sweep(H, [l](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF[l]; }, kModeChain, st)) !=
+  auto fl = [l](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF[l]; };
+  // FCF-relaxation, then the C-point residuals injected into the next level
+  if ((e = sweep(H, fl, kModeChain, st)) != hipSuccess) return e;
+  if ((e = sweep(H, [l](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jC[l]; }, kModeChain, st)) !=
       hipSuccess)
     return e;
-  if ((e = sweep(H, [l](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jCF[l]; }, kModeChain, st)) !=
-      hipSuccess)
-    return e;
+  if ((e = sweep(H, fl, kModeChain, st)) != hipSuccess) return e;
   if ((e = sweep(H, [l](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jRES[l]; }, kModeResidual,
                  st)) != hipSuccess)
     return e;
-  phi += 2 * sweep_steps(H, 0, l) + sweep_steps(H, 1, l) + sweep_steps(H, 2, l);
+  // F, C, F, residual, and the interpolating F-relaxation after the correction
+  phi += 3 * sweep_steps(H, 0, l) + sweep_steps(H, 1, l) + sweep_steps(H, 2, l);
   for (int i = 0; i < H->ninst; ++i) {
     double* vc = H->h_vtab[(size_t)i * kMaxLevels + l + 1];
     if ((e = fill_launch(vc, (int64_t)(H->Nl[l + 1] + 1) * H->inst[i].ndof, 0.0, st)) != hipSuccess) return e;
@@ -1184,7 +1185,7 @@ pmgrit_status pmgrit_create(int32_t n_instances, const pmgrit_problem* probs, co
     return fail(PMGRIT_E_ARG, "invalid MGRIT options");
   if (so.nu1 < 1 || so.nu2 < 0 || !(so.ilut_droptol >= 0) || !(so.spatial_tol > 0) || so.max_vcycles < 1 ||
       (so.precision != 0 && so.precision != 1) || so.guess < 0 || so.guess > 3 || so.trsv_block < -1 ||
-      so.autotune < 0 || so.autotune > 1)
+      so.autotune < 0 || so.autotune > 1 || !(so.coarse_tol >= 0) || so.coarse_tol >= 1)
     return fail(PMGRIT_E_ARG, "invalid solver options");
   for (int i = 0; i < n_instances; ++i) {
     const pmgrit_problem& p = probs[i];
@@ -1373,17 +1374,17 @@ static hipError_t relax_level0(pmgrit_handle* h, hipStream_t st, bool learned, i
     };
     if ((e = fsplit()) != hipSuccess) return e;
     if ((e = net_predict(h, 2, 0, 0, st)) != hipSuccess) return e;
-    if ((e = sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jC1; }, kModeChain, st, 4)) !=
+    if ((e = sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jC[0]; }, kModeChain, st, 4)) !=
         hipSuccess)
       return e;
     if ((e = fsplit()) != hipSuccess) return e;
   } else {
-    if ((e = sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF[0]; }, kModeChain, st)) !=
+    auto f0 = [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF[0]; };
+    if ((e = sweep(h, f0, kModeChain, st)) != hipSuccess) return e;
+    if ((e = sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jC[0]; }, kModeChain, st)) !=
         hipSuccess)
       return e;
-    if ((e = sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jCF[0]; }, kModeChain, st)) !=
-        hipSuccess)
-      return e;
+    if ((e = sweep(h, f0, kModeChain, st)) != hipSuccess) return e;
   }
   if ((e = sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jRES[0]; }, kModeResidual,
                  st)) != hipSuccess)
@@ -1844,13 +1845,22 @@ pmgrit_status pmgrit_net_train(pmgrit_handle* h, const pmgrit_train_opts* opts, 
     return fail(PMGRIT_E_ARG, "bad training arguments");
   TRY(net_ready(h));
   if (!h->net->loaded) return fail(PMGRIT_E_STATE, "no network loaded");
-  const int G = h->inst[0].Nin + 2;
-  for (int i = 0; i < h->ninst; ++i) {
+  for (int i = 0; i < h->ninst; ++i)
     if (!U_dev[i]) return fail(PMGRIT_E_ARG, "U_dev[i] is NULL");
-    if (h->inst[i].Nin + 2 != G) return fail(PMGRIT_E_ARG, "training needs one grid size for all instances");
-  }
   hipStream_t st = (hipStream_t)hip_stream;
   auto t0 = std::chrono::steady_clock::now();
+  // samples grouped by grid size (a batch has one grid size); batches of the groups interleaved
+  std::vector<int> gsz;
+  std::vector<std::vector<int>> ginst;
+  for (int i = 0; i < h->ninst; ++i) {
+    const int G = h->inst[i].Nin + 2;
+    size_t q = std::find(gsz.begin(), gsz.end(), G) - gsz.begin();
+    if (q == gsz.size()) {
+      gsz.push_back(G);
+      ginst.emplace_back();
+    }
+    ginst[q].push_back(i);
+  }
   std::vector<NetSrc> src(h->h_netsrc, h->h_netsrc + h->ninst);
   for (int i = 0; i < h->ninst; ++i) src[i].U = U_dev[i];
   NetSrc* d_src = nullptr;
@@ -1861,30 +1871,49 @@ pmgrit_status pmgrit_net_train(pmgrit_handle* h, const pmgrit_train_opts* opts, 
   HIPCHK(hipMalloc(&d_pick, sizeof(NetPick) * total));
   std::unique_ptr<void, void (*)(void*)> g2(d_pick, [](void* p) { (void)hipFree(p); });
   HIPCHK(hipMemcpy(d_src, src.data(), sizeof(NetSrc) * h->ninst, hipMemcpyHostToDevice));
-  HIPCHK(h->net->reserve(opts->batch, G));
+  for (int G : gsz) HIPCHK(h->net->reserve(opts->batch, G));
   pmgrit_train_stats S;
   std::memset(&S, 0, sizeof(S));
-  std::vector<std::pair<uint64_t, int64_t>> key(total);
   std::vector<NetPick> order(total);
   for (int ep = 0; ep < opts->epochs; ++ep) {
-    for (int64_t q = 0; q < total; ++q)
-      key[q] = {mix64(((uint64_t)opts->seed << 40) ^ ((uint64_t)ep << 32) ^ (uint64_t)q), q};
-    std::sort(key.begin(), key.end());
-    for (int64_t q = 0; q < total; ++q)
-      order[q] = {(int)(key[q].second / h->Nt), (int)(key[q].second % h->Nt)};
+    // per group: its samples sorted by a counter-based hash of (seed, epoch, sample)
+    std::vector<int64_t> gbeg(gsz.size() + 1, 0);
+    int64_t o = 0;
+    for (size_t q = 0; q < gsz.size(); ++q) {
+      std::vector<std::pair<uint64_t, NetPick>> key;
+      for (int i : ginst[q])
+        for (int k = 0; k < h->Nt; ++k) {
+          const uint64_t id = (uint64_t)i * (uint64_t)h->Nt + (uint64_t)k;
+          key.push_back({mix64(((uint64_t)opts->seed << 40) ^ ((uint64_t)ep << 32) ^ id), NetPick{i, k}});
+        }
+      std::sort(key.begin(), key.end(),
+                [](const std::pair<uint64_t, NetPick>& a, const std::pair<uint64_t, NetPick>& b) {
+                  return a.first < b.first;
+                });
+      gbeg[q] = o;
+      for (auto& kv : key) order[o++] = kv.second;
+    }
+    gbeg[gsz.size()] = o;
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipMemcpy(d_pick, order.data(), sizeof(NetPick) * total, hipMemcpyHostToDevice));
     double lsum = 0.0;
     int64_t nbat = 0;
-    for (int64_t q0 = 0; q0 < total; q0 += opts->batch) {
-      const int nb = (int)std::min<int64_t>(opts->batch, total - q0);
-      HIPCHK(h->net->train_packed(d_src, d_pick + q0, nb, G, opts->lr, st));
-      double l = 0.0;
-      HIPCHK(h->net->read_loss(&l, st));
-      if (S.adam_steps == 0) S.loss_first = l;
-      ++S.adam_steps;
-      lsum += l;
-      ++nbat;
+    std::vector<int64_t> pos(gbeg.begin(), gbeg.end() - 1);
+    for (bool any = true; any;) {
+      any = false;
+      for (size_t q = 0; q < gsz.size(); ++q) {
+        if (pos[q] >= gbeg[q + 1]) continue;
+        any = true;
+        const int nb = (int)std::min<int64_t>(opts->batch, gbeg[q + 1] - pos[q]);
+        HIPCHK(h->net->train_packed(d_src, d_pick + pos[q], nb, gsz[q], opts->lr, st));
+        pos[q] += nb;
+        double l = 0.0;
+        HIPCHK(h->net->read_loss(&l, st));
+        if (S.adam_steps == 0) S.loss_first = l;
+        ++S.adam_steps;
+        lsum += l;
+        ++nbat;
+      }
     }
     S.loss_last = nbat ? lsum / nbat : 0.0;
     S.epochs_done = ep + 1;

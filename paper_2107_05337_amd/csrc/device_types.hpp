@@ -103,7 +103,8 @@ struct PhiParams {
   int64_t ws_stride;       // doubles per workgroup
   int mode, guess, maxcyc, nu1, nu2;
   int kshift;              // added to every job's first point (one job list serves all steps)
-  double stol;
+  double stol;             // spatial tolerance at level 0
+  double stolc;            // spatial tolerance at coarse levels
 };
 
 // LDS placement of the work vectors (byte offsets, -1 = global scratch)

@@ -449,6 +449,24 @@ __global__ void __launch_bounds__(256) net_convert(const float* __restrict__ th,
   }
 }
 
+// zero the halo ring and slack pixels of every sample for grid size G (all other pixels are
+// written before they are read): 4 (G + 1) ring pixels + 32 slack pixels, 32 channels each
+__global__ void __launch_bounds__(256) net_halo_zero(uint16_t* __restrict__ a, int nb, int G) {
+  const int P = G + 2, ring = 4 * (G + 1), per = ring + 32;
+  const int64_t SS = sample_stride(G), tot = (int64_t)nb * per * 4;  // 4 16-byte chunks per pixel
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < tot; t += (int64_t)gridDim.x * 256) {
+    const int n = (int)(t / (per * 4)), rem = (int)(t % (per * 4)), px = rem >> 2, c = rem & 3;
+    int64_t q;
+    if (px < P) q = px;                                    // top row
+    else if (px < 2 * P) q = (int64_t)(P - 1) * P + (px - P);  // bottom row
+    else if (px < ring) {                                  // left / right columns of rows 1 .. P-2
+      const int k = px - 2 * P, row = 1 + (k >> 1);
+      q = (int64_t)row * P + ((k & 1) ? P - 1 : 0);
+    } else q = (int64_t)P * P + (px - ring);               // slack
+    ((uint4*)(a + ((int64_t)n * SS + q) * 32))[c] = make_uint4(0u, 0u, 0u, 0u);
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // samples from trajectories
 // ---------------------------------------------------------------------------------------------
@@ -605,16 +623,15 @@ hipError_t NetState::reserve(int nb, int G) {
 }
 
 // the halo ring of the activation grids must be zero: when the grid size changes, positions that
-// held interior pixels may become halo, so the activation buffers are cleared
+// held interior pixels may become halo, so the new layout's halo and slack pixels are cleared (a
+// kernel, so this may also sit in a captured graph)
 hipError_t NetState::layout(int G, hipStream_t st) {
   if (G == G_last_) return hipSuccess;
-  const size_t act = (size_t)nb_cap_ * sample_stride(G_cap_) * 32 * sizeof(uint16_t);
-  for (uint16_t* p : {a0_, a1_, a2_, ga_, gb_}) {
-    hipError_t e = hipMemsetAsync(p, 0, act, st);
-    if (e != hipSuccess) return e;
-  }
+  const int64_t work = (int64_t)nb_cap_ * (4 * (G + 1) + 32) * 4;
+  const int grid = grid_for(work, 256, 4096);
+  for (uint16_t* p : {a0_, a1_, a2_, ga_, gb_}) hipLaunchKernelGGL(net_halo_zero, dim3(grid), dim3(256), 0, st, p, nb_cap_, G);
   G_last_ = G;
-  return hipSuccess;
+  return hipGetLastError();
 }
 
 hipError_t NetState::run_forward(int nb, int G, const float* x, float* y, hipStream_t st) {

@@ -525,7 +525,7 @@ __global__ void __launch_bounds__(Cfg<VT>::NT) phi_kernel(PhiParams P, LdsPlan p
   const double* Gl = (P.gtab && job.level > 0) ? P.gtab[job.inst * kMaxLevels + job.level] : nullptr;
   const double* Fv = I.F;
   const double* scale = I.scale;
-  const double stol2 = P.stol * P.stol;
+  const double stol2 = job.level == 0 ? P.stol * P.stol : P.stolc * P.stolc;
   int total = 0;
   for (int st = 0; st < job.len; ++st) {
     const int k = job.k0 + P.kshift + st;  // step from point k to point k + 1

@@ -34,13 +34,13 @@ def torch():
     return T
 
 
-def make_solver(cfg, precision=0, guess=2, trsv_block=-1, tol=1e-10, stol=1e-12, autotune=0, **mo):
+def make_solver(cfg, precision=0, guess=2, trsv_block=-1, tol=1e-10, stol=1e-12, autotune=0, ctol=0.0, **mo):
     probs = [pm.problem(d["p"], d["n"], d["Nt"], kappa=d["kappa"], T=d["T"], domain=d["domain"])
              for d in cfg["instances"]]
     mopts = pm.default_mgrit_opts(cfactor=cfg["m"], max_levels=cfg["max_levels"], coarsest_max=cfg["coarsest_max"],
                                   tol=tol, **mo)
     sopts = pm.default_solver_opts(precision=precision, guess=guess, trsv_block=trsv_block, spatial_tol=stol,
-                                   autotune=autotune)
+                                   autotune=autotune, coarse_tol=ctol)
     S = pm.Solver(probs, mopts, sopts, device=0)
     for i, d in enumerate(cfg["instances"]):
         S.set_source(i, d["src"], d["tkind"])
@@ -238,3 +238,24 @@ def test_autotune_same_result(torch, precision):
     (U1,), st1 = S1.solve_mgrit()
     assert gi["lds_mask"] & 1
     assert torch.equal(U0, U1) and st0["vcycles"] == st1["vcycles"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_coarse_tolerance(torch, precision):
+    """Looser spatial solves on the coarse levels: same converged answer, same iteration count as
+    the oracle's MGRIT with the same coarse tolerance."""
+    cfg = W.small("x", 3, 16, 512)
+    cfg["m"], cfg["max_levels"], cfg["coarsest_max"] = 8, 12, 8
+    d = cfg["instances"][0]
+    say(f"case coarse tolerance 1e-6 precision={precision}")
+    S = make_solver(cfg, precision=precision, tol=1e-11, ctol=1e-6)
+    (U,), st = S.solve_mgrit()
+    assert rel(U.cpu().numpy(), oracle_sequential(d)) <= EPS
+    P = O.Problem(d["p"], d["n"], 0)
+    r = P.mgrit(d["kappa"], d["T"], d["Nt"], P.load_vector(d["src"]), d["tkind"], P.project(d["init"]), m=8,
+                tol=1e-11, ctol=1e-6)
+    S0 = make_solver(cfg, precision=precision, tol=1e-11)
+    _, st0 = S0.solve_mgrit()
+    say(f"  iters {st['mgrit_iters']} (oracle {r['iters']}), V-cycles {st['vcycles']} vs {st0['vcycles']} at 1e-12")
+    assert abs(st["mgrit_iters"] - r["iters"]) <= 1
+    assert st["vcycles"] < st0["vcycles"]
