@@ -237,6 +237,49 @@ def c4_learned(n_train: int = 64, epochs: int = 4, batch: int = 128, lr: float =
             "evaluation": "4 unseen sources (seeds 1000..1003), one handle, spatial tol 1e-12", "guesses": res}
 
 
+NET_MACS_PER_PIXEL = 9 * (3 * 32 + 32 * 32 + 32 * 32 + 32 * 1)
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def net_bench(nb: int = 256, G: int = 67, reps: int = 20):
+    """Throughput of the warm-start network kernels on a batch of nb samples of a G x G grid:
+    inference and loss gradient (forward + backward), HIP-event timed on the current stream."""
+    import numpy as np
+    import torch
+
+    import paper_2107_05337_amd as pm
+    from paper_2107_05337_amd import workloads as W
+
+    S = pm.Solver([pm.problem(3, G - 3, 8)], pm.default_mgrit_opts(), pm.default_solver_opts(), device=0)
+    S.net_load(W.net_init(0).astype(np.float32))
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((nb, 3, G, G), generator=g, device="cuda")
+    t = torch.randn((nb, G, G), generator=g, device="cuda")
+    y = torch.empty((nb, G, G), device="cuda")
+    fwd = 2.0 * NET_MACS_PER_PIXEL * G * G * nb
+    out = {}
+    for name, fn, flops in (("forward", lambda: S.net_forward(x, y), fwd),
+                            ("forward+backward", lambda: S.net_grad(x, t), 3.0 * fwd)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = dict(ms=round(ms, 4), tflops=round(flops / ms * 1e-9, 2),
+                         frac_bf16_peak=round(flops / ms * 1e-9 / BF16_PEAK_TFLOPS, 5))
+    S.close()
+    return {"experiment": "warm-start network kernels", "batch": nb, "grid": G,
+            "flop_per_sample_forward": 2 * NET_MACS_PER_PIXEL * G * G, "peak_tflops_bf16": BF16_PEAK_TFLOPS,
+            "note": "forward+backward counted as 3x forward (the first layer's input gradient is not formed); "
+                    "net_grad also copies the gradient to the host",
+            "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +287,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--variants", default="fp64,fp32,fp32+tuned,fp32+learned")
     ap.add_argument("--c4", action="store_true", help="run the learned-warm-start measurement instead")
+    ap.add_argument("--net", action="store_true", help="time the network kernels instead")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 512 MiB device copy (counter calibration) and exit")
@@ -261,6 +305,9 @@ def main():
         return
     if args.c4:
         print(json.dumps(c4_learned()))
+        return
+    if args.net:
+        print(json.dumps(net_bench()))
         return
     specs = {"fp64": dict(precision=0), "fp32": dict(precision=1),
              "fp32+tuned": dict(precision=1, autotune=1, graph=1, coarse_tol=1e-6),

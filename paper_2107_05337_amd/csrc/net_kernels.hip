@@ -251,28 +251,37 @@ __global__ void __launch_bounds__(256) net_out_bwd_data(const float* __restrict_
   }
 }
 
-// last-layer weight gradient partials: thread j < 288 = (tap, ci) sums dy[q] a2[q + o_t][ci] over its
-// block's pixel range, thread 288 sums dy (the bias)
-__global__ void __launch_bounds__(320) net_out_wgrad(const float* __restrict__ dy, const uint16_t* __restrict__ a2,
-                                                     float* __restrict__ part, int nb, int G, int64_t chunk) {
-  const int j = threadIdx.x;
-  if (j > 288) return;
+// last-layer weight gradient partials: 8 pixel slots x 32 channels per workgroup; thread (slot,
+// ci) accumulates dy[q] a2[q + o_t][ci] for the 9 taps (and dy for the bias) over its pixels,
+// then the slots are summed in a fixed order
+__global__ void __launch_bounds__(256) net_out_wgrad(const float* __restrict__ dy, const uint16_t* __restrict__ a2,
+                                                     float* __restrict__ part, int nb, int G) {
+  __shared__ float red[8 * kP3];
+  const int ci = threadIdx.x & 31, ps = threadIdx.x >> 5;
   const int P = G + 2;
   const int64_t SS = sample_stride(G), tot = (int64_t)nb * G * G;
-  const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = p0 + chunk < tot ? p0 + chunk : tot;
-  const int t = j / 32, ci = j % 32;
-  float acc = 0.f;
-  for (int64_t pix = p0; pix < p1; ++pix) {
+  float acc[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc[t] = 0.f;
+  float bacc = 0.f;
+  for (int64_t pix = (int64_t)blockIdx.x * 8 + ps; pix < tot; pix += (int64_t)gridDim.x * 8) {
     const float g = dy[pix];
-    if (g == 0.f) continue;  // uniform over the block
-    if (j == 288) {
-      acc += g;
-    } else {
-      const int n = (int)(pix / (G * G)), r = (int)(pix % (G * G)), yy = r / G, xx = r % G;
-      acc += g * bf2f(a2[((int64_t)n * SS + (int64_t)(yy + t / 3) * P + xx + t % 3) * 32 + ci]);
-    }
+    const int n = (int)(pix / (G * G)), r = (int)(pix % (G * G)), yy = r / G, xx = r % G;
+    const uint16_t* base = a2 + ((int64_t)n * SS + (int64_t)yy * P + xx) * 32 + ci;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] += g * bf2f(base[((t / 3) * P + t % 3) * 32]);
+    bacc += g;
   }
-  part[(int64_t)blockIdx.x * kP3 + j] = acc;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) red[ps * kP3 + t * 32 + ci] = acc[t];
+  if (ci == 0) red[ps * kP3 + 288] = bacc;
+  __syncthreads();
+  for (int j = threadIdx.x; j < kP3; j += 256) {
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += red[q * kP3 + j];
+    part[(int64_t)blockIdx.x * kP3 + j] = s;
+  }
 }
 
 // 32 -> 32 weight gradient on the matrix cores: dW[t][co][ci] = sum_q g[q][co] a[q + o_t][ci].
@@ -358,58 +367,114 @@ __global__ void __launch_bounds__(576) net_conv32_wgrad(const uint16_t* __restri
   if (threadIdx.x < 32) pr[9216 + threadIdx.x] = bacc;
 }
 
-// first-layer weight gradient partials: thread j < 864 = (tap, ci, co) sums g0[q][co] x[ci][q + o_t]
-// (inputs rounded to BF16 as in the forward pass); threads 864..895 sum g0 (the biases)
-__global__ void __launch_bounds__(896) net_in_wgrad(const float* __restrict__ x, const uint16_t* __restrict__ g0,
-                                                    float* __restrict__ part, int nb, int G, int64_t chunk) {
-  const int j = threadIdx.x;
+// first-layer weight gradient partials on the matrix cores: dW0[t][ci][co] = sum_q g0[q][co]
+// x[ci][q + o_t] as a 32 x 32 product per 32-pixel row segment (K = pixels, M = co, N = the 27
+// (tap, ci) pairs padded to 32), the inputs rounded to BF16 as in the forward pass.  One wave per
+// workgroup stages g0^T ([co][px]) and the shifted inputs ([tap ci][px]) in LDS; lane c < 32 also
+// sums g0[.][c] (the bias).
+constexpr int kInBlocks = 1024;
+__global__ void __launch_bounds__(64) net_in_wgrad(const float* __restrict__ x, const uint16_t* __restrict__ g0,
+                                                   float* __restrict__ part, int nb, int G) {
+  __shared__ __align__(16) uint16_t gT[32 * 32];
+  __shared__ __align__(16) uint16_t xT[32 * 32];
+  const int lane = threadIdx.x, m16 = lane & 15, kq = lane >> 4;
   const int P = G + 2;
-  const int64_t SS = sample_stride(G), tot = (int64_t)nb * G * G;
-  const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = p0 + chunk < tot ? p0 + chunk : tot;
-  const bool wt = j < 864;
-  const int t = wt ? j / 96 : 0, ci = wt ? (j / 32) % 3 : 0, co = wt ? j % 32 : j - 864;
-  float acc = 0.f;
-  for (int64_t pix = p0; pix < p1; ++pix) {
-    const int n = (int)(pix / (G * G)), r = (int)(pix % (G * G)), yy = r / G, xx = r % G;
-    const float gv = bf2f(g0[((int64_t)n * SS + (int64_t)(yy + 1) * P + xx + 1) * 32 + co]);
-    if (wt) {
-      const int Y = yy + t / 3 - 1, X = xx + t % 3 - 1;
-      if (Y >= 0 && Y < G && X >= 0 && X < G) acc += gv * bfround(x[(((int64_t)n * 3 + ci) * G + Y) * G + X]);
-    } else {
-      acc += gv;
+  const int64_t SS = sample_stride(G);
+  const int xs = (G + 31) / 32;
+  const int64_t nseg = (int64_t)nb * G * xs;
+  for (int e = lane; e < 5 * 32; e += 64) xT[27 * 32 + e] = 0;  // padding rows 27..31
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) acc[i][k] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.f;
+  for (int64_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+    const int n = (int)(seg / ((int64_t)G * xs));
+    const int rem = (int)(seg % ((int64_t)G * xs));
+    const int yy = rem / xs, x0 = (rem % xs) * 32;
+    __syncthreads();  // the previous segment's fragments have been read
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // g0: 32 px x 4 groups of 8 channels
+      const int c = lane + 64 * h, px = c >> 2, c8 = (c & 3) * 8;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (x0 + px < G) v = *(const uint4*)(g0 + ((int64_t)n * SS + (int64_t)(yy + 1) * P + x0 + px + 1) * 32 + c8);
+      const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        gT[(c8 + 2 * e) * 32 + px] = (uint16_t)(wd[e] & 0xffffu);
+        gT[(c8 + 2 * e + 1) * 32 + px] = (uint16_t)(wd[e] >> 16);
+      }
     }
+    for (int e = lane; e < 27 * 32; e += 64) {  // inputs: row tci = 3 t + ci, column px
+      const int tci = e >> 5, px = e & 31, t = tci / 3, ci = tci - 3 * t;
+      const int Y = yy + t / 3 - 1, X = x0 + px + t % 3 - 1;
+      float v = 0.f;
+      if (x0 + px < G && Y >= 0 && Y < G && X >= 0 && X < G) v = x[(((int64_t)n * 3 + ci) * G + Y) * G + X];
+      xT[e] = f2bf(v);
+    }
+    __syncthreads();
+    bf16x8 A[2], B[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      A[h] = *(const bf16x8*)(gT + (h * 16 + m16) * 32 + 8 * kq);
+      B[h] = *(const bf16x8*)(xT + (h * 16 + m16) * 32 + 8 * kq);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) acc[i][k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], B[k], acc[i][k], 0, 0, 0);
+    if (lane < 32)
+      for (int px = 0; px < 32; ++px) bacc += bf2f(gT[lane * 32 + px]);
   }
-  part[(int64_t)blockIdx.x * kP0 + j] = acc;
+  float* pr = part + (int64_t)blockIdx.x * kP0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int co = i * 16 + 4 * kq + e, tci = k * 16 + m16;
+        if (tci < 27) pr[tci * 32 + co] = acc[i][k][e];
+      }
+  if (lane < 32) pr[864 + lane] = bacc;
 }
 
 // sum the partial records of every layer into the flat gradient (fixed order: deterministic)
+// (64 parameters per workgroup, 4 lanes per parameter summing every 4th record, combined in LDS)
 __global__ void __launch_bounds__(256) net_reduce(const float* __restrict__ p0, const float* __restrict__ p1,
                                                   const float* __restrict__ p2, const float* __restrict__ p3,
-                                                  int nblk, float* __restrict__ grad) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= kNetParams) return;
-  const float* src;
-  int stride, off;
-  if (i < kB0) {  // W0[co][ci][t]
-    const int co = i / 27, ci = (i / 9) % 3, t = i % 9;
-    src = p0, stride = kP0, off = (t * 3 + ci) * 32 + co;
-  } else if (i < kW1) {
-    src = p0, stride = kP0, off = 864 + (i - kB0);
-  } else if (i < kB1 || (i >= kW2 && i < kB2)) {  // W1, W2 [co][ci][t]
-    const int l = i < kB1 ? i - kW1 : i - kW2;
-    const int co = l / 288, ci = (l / 9) % 32, t = l % 9;
-    src = i < kB1 ? p1 : p2, stride = kP1, off = (t * 32 + co) * 32 + ci;
-  } else if (i < kW2 || (i >= kB2 && i < kW3)) {
-    src = i < kW2 ? p1 : p2, stride = kP1, off = 9216 + (i < kW2 ? i - kB1 : i - kB2);
-  } else if (i < kB3) {  // W3[0][ci][t]
-    const int l = i - kW3, ci = l / 9, t = l % 9;
-    src = p3, stride = kP3, off = t * 32 + ci;
-  } else {
-    src = p3, stride = kP3, off = 288;
-  }
+                                                  int nblk, int nblk0, float* __restrict__ grad) {
+  __shared__ float red[256];
+  const int i = blockIdx.x * 64 + (threadIdx.x >> 2), q = threadIdx.x & 3;
   float s = 0.f;
-  for (int b = 0; b < nblk; ++b) s += src[(int64_t)b * stride + off];
-  grad[i] = s;
+  if (i < kNetParams) {
+    const float* src;
+    int stride, off;
+    if (i < kB0) {  // W0[co][ci][t]
+      const int co = i / 27, ci = (i / 9) % 3, t = i % 9;
+      src = p0, stride = kP0, off = (t * 3 + ci) * 32 + co;
+    } else if (i < kW1) {
+      src = p0, stride = kP0, off = 864 + (i - kB0);
+    } else if (i < kB1 || (i >= kW2 && i < kB2)) {  // W1, W2 [co][ci][t]
+      const int l = i < kB1 ? i - kW1 : i - kW2;
+      const int co = l / 288, ci = (l / 9) % 32, t = l % 9;
+      src = i < kB1 ? p1 : p2, stride = kP1, off = (t * 32 + co) * 32 + ci;
+    } else if (i < kW2 || (i >= kB2 && i < kW3)) {
+      src = i < kW2 ? p1 : p2, stride = kP1, off = 9216 + (i < kW2 ? i - kB1 : i - kB2);
+    } else if (i < kB3) {  // W3[0][ci][t]
+      const int l = i - kW3, ci = l / 9, t = l % 9;
+      src = p3, stride = kP3, off = t * 32 + ci;
+    } else {
+      src = p3, stride = kP3, off = 288;
+    }
+    const int nbk = src == p0 ? nblk0 : nblk;
+    for (int b = q; b < nbk; b += 4) s += src[(int64_t)b * stride + off];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (q == 0 && i < kNetParams)
+    grad[i] = (red[threadIdx.x] + red[threadIdx.x + 1]) + (red[threadIdx.x + 2] + red[threadIdx.x + 3]);
 }
 
 // Adam (Kingma and Ba), bias-corrected: c1 = 1 - 0.9^step, c2 = 1 - 0.999^step
@@ -567,7 +632,7 @@ hipError_t NetState::init(int device) {
       (e = alloc(&wf1_, 9216)) || (e = alloc(&wb1_, 9216)) || (e = alloc(&wf2_, 9216)) || (e = alloc(&wb2_, 9216)) ||
       (e = alloc(&loss_, 1)) || (e = alloc(&lpart_, 1024)))
     return e;
-  part_cap_ = (int64_t)kPartBlocks * (kP0 + 2 * kP1 + kP3);
+  part_cap_ = (int64_t)kInBlocks * kP0 + (int64_t)kPartBlocks * (2 * kP1 + kP3);
   return alloc(&part_, (size_t)part_cap_);
 }
 
@@ -654,18 +719,17 @@ hipError_t NetState::run_backward(int nb, int G, const float* x, const float* t,
   const int gl = grid_for(pix, 256, 1024);
   const int64_t tiles = (int64_t)nb * G * ((G + 15) / 16);
   const int gt = grid_for(tiles, 4, 4096);
-  const int64_t chunk = (pix + kPartBlocks - 1) / kPartBlocks;
   const int nseg = (int)((int64_t)nb * G * ((G + 31) / 32) < kPartBlocks ? (int64_t)nb * G * ((G + 31) / 32)
                                                                          : kPartBlocks);
   float* p0 = part_;
-  float* p1 = p0 + (int64_t)kPartBlocks * kP0;
+  float* p1 = p0 + (int64_t)kInBlocks * kP0;
   float* p2 = p1 + (int64_t)kPartBlocks * kP1;
   float* p3 = p2 + (int64_t)kPartBlocks * kP1;
   const double cnt = (double)nb * (G - 2) * (G - 2);
   hipLaunchKernelGGL(net_loss, dim3(gl), dim3(256), 0, st, y_, t, dy_, lpart_, nb, G, (float)(2.0 / cnt));
   hipLaunchKernelGGL(net_sum, dim3(1), dim3(256), 0, st, lpart_, gl, 1.0 / cnt, loss_);
   // layer 3
-  hipLaunchKernelGGL(net_out_wgrad, dim3(kPartBlocks), dim3(320), 0, st, dy_, a2_, p3, nb, G, chunk);
+  hipLaunchKernelGGL(net_out_wgrad, dim3(kPartBlocks), dim3(256), 0, st, dy_, a2_, p3, nb, G);
   hipLaunchKernelGGL(net_out_bwd_data, dim3(gp), dim3(256), 0, st, dy_, w3_, a2_, ga_, nb, G);
   // layer 2: weights from (a1, ga), input gradient ga -> gb masked by a1
   if (nseg < kPartBlocks) {
@@ -678,9 +742,9 @@ hipError_t NetState::run_backward(int nb, int G, const float* x, const float* t,
   hipLaunchKernelGGL(net_conv32_wgrad, dim3(nseg), dim3(576), 0, st, a0_, gb_, p1, nb, G);
   hipLaunchKernelGGL(net_conv32<1>, dim3(gt), dim3(256), 0, st, gb_, wb1_, nullptr, a0_, ga_, nb, G);
   // layer 0
-  hipLaunchKernelGGL(net_in_wgrad, dim3(kPartBlocks), dim3(896), 0, st, x, ga_, p0, nb, G, chunk);
-  hipLaunchKernelGGL(net_reduce, dim3((kNetParams + 255) / 256), dim3(256), 0, st, p0, p1, p2, p3, kPartBlocks,
-                     grad_);
+  hipLaunchKernelGGL(net_in_wgrad, dim3(kInBlocks), dim3(64), 0, st, x, ga_, p0, nb, G);
+  hipLaunchKernelGGL(net_reduce, dim3((kNetParams + 63) / 64), dim3(256), 0, st, p0, p1, p2, p3, kPartBlocks,
+                     kInBlocks, grad_);
   return hipGetLastError();
 }
 
