@@ -757,7 +757,10 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
         // off-block entries per lane of the prefetched triangular solves: the widest ILUT row
         // of the group's instances over the 4 lanes per row, rounded up to a power of two
         const int maxo = inst_max_offblock(I);
-        while (G.ka * 4 < maxo && G.ka < 16) G.ka *= 2;
+        // ka in {2, 4, 8, 12, 16}: 16-byte units of 4 entries per lane beyond 2
+        const int need = (maxo + 3) / 4;
+        const int ka = need <= 2 ? 2 : std::min(16, (need + 3) / 4 * 4);
+        G.ka = std::max(G.ka, ka);
       }
       G.rw = G.ka * 4;
       lds_plan(G.nmax, G.n1max, G.maxrows, vt, G.ka, dev_lds, G.mask, G.lds_bytes, G.plan);

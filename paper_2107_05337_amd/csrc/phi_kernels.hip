@@ -86,6 +86,8 @@ __device__ __forceinline__ const G<float>* band_ptr<float>(const BandDev& B) {
 // sum-factorised Kronecker passes
 // ---------------------------------------------------------------------------------------
 
+constexpr int kBandMax = 11;  // widest 1D band: 2p + 1 at p = 5
+
 // first-direction pass: T[r][o] = sum_d B[o][d] * in[r][o + lo + d] for r < nrows, o < B.rows
 // (in has nin columns; band entries outside the input range are zero, their index is clamped)
 template <int NT, typename AT, typename IT, typename OT>
@@ -97,11 +99,23 @@ __device__ __forceinline__ void pass_x(int nrows, int nin, const BandDev& Bd, co
     const int r = t / nout, o = t - r * nout;
     const IT* src = in + r * nin;
     const G<AT>* b = B + o * w;
+    // unrolled to the widest band of p <= 5 with clamped addresses, so every load of the output
+    // issues at once (wider bands take the loop)
     AT s = 0;
-    for (int d = 0; d < w; ++d) {
-      int j = o + lo + d;
-      j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
-      s += b[d] * (AT)src[j];
+    if (w <= kBandMax) {
+#pragma unroll
+      for (int d = 0; d < kBandMax; ++d) {
+        int j = o + lo + d;
+        j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+        const AT bd = b[d < w ? d : w - 1];
+        s += (d < w ? bd : (AT)0) * (AT)src[j];
+      }
+    } else {
+      for (int d = 0; d < w; ++d) {
+        int j = o + lo + d;
+        j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+        s += b[d] * (AT)src[j];
+      }
     }
     out[t] = (OT)s;
   }
@@ -122,10 +136,20 @@ __device__ __forceinline__ double pass_y(int ncols, int nin, const BandDev& Bd, 
     const int o = t / ncols, c = t - o * ncols;
     const G<AT>* b = B + o * w;
     AT s = 0;
-    for (int d = 0; d < w; ++d) {
-      int j = o + lo + d;
-      j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
-      s += b[d] * (AT)T[j * ncols + c];
+    if (w <= kBandMax) {
+#pragma unroll
+      for (int d = 0; d < kBandMax; ++d) {
+        int j = o + lo + d;
+        j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+        const AT bd = b[d < w ? d : w - 1];
+        s += (d < w ? bd : (AT)0) * (AT)T[j * ncols + c];
+      }
+    } else {
+      for (int d = 0; d < w; ++d) {
+        int j = o + lo + d;
+        j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+        s += b[d] * (AT)T[j * ncols + c];
+      }
     }
     AT v = alpha * s;
     if (scy) v *= (AT)(gp(scy)[o] * gp(scx)[c]);
@@ -371,6 +395,8 @@ __device__ __forceinline__ void trsv(const TriDev& T, int ka, const VT* in, VT* 
       trsv_fast<VT, IN_GLOBAL, 4>(&T, in, yl, sl);
     else if (ka <= 8)
       trsv_fast<VT, IN_GLOBAL, 8>(&T, in, yl, sl);
+    else if (ka <= 12)
+      trsv_fast<VT, IN_GLOBAL, 12>(&T, in, yl, sl);
     else
       trsv_fast<VT, IN_GLOBAL, 16>(&T, in, yl, sl);
   } else {
@@ -383,17 +409,47 @@ __device__ __forceinline__ void trsv(const TriDev& T, int ka, const VT* in, VT* 
 // exact p = 1 solve: fast diagonalisation c = V diag-solve(V^T c), one symmetric tridiagonal
 // system per mode of the second direction (Thomas, precomputed LDL^T).  c1 in / out, c2 temp.
 // ---------------------------------------------------------------------------------------
+// dense transform over the second direction, out[a][ix] = sum_b W(a, b) in[b][ix] for a, ix < n1,
+// with W(a, b) = V[b][a] (transposed) or V[a][b]: 4 x 4 output tiles per thread, so each loaded
+// V entry and input entry serves four products
+template <int NT, bool TRANS>
+__device__ __forceinline__ void coarse_transform(int n1, const G<double>* __restrict__ V, const double* in,
+                                                 double* out) {
+  const int nt = (n1 + 3) / 4, tiles = nt * nt;
+  for (int t = threadIdx.x; t < tiles; t += NT) {
+    const int a0 = (t / nt) * 4, x0 = (t % nt) * 4;
+    double acc[4][4] = {};
+    int ia[4], ix[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ia[u] = a0 + u < n1 ? a0 + u : n1 - 1;  // clamped: rows / columns past n1 are not stored
+      ix[u] = x0 + u < n1 ? x0 + u : n1 - 1;
+    }
+    for (int b = 0; b < n1; ++b) {
+      double w[4], v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        w[u] = TRANS ? V[b * n1 + ia[u]] : V[ia[u] * n1 + b];
+        v[u] = in[b * n1 + ix[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[u][q] += w[u] * v[q];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (a0 + u < n1 && x0 + q < n1) out[(a0 + u) * n1 + x0 + q] = acc[u][q];
+  }
+}
+
 template <int NT>
 __device__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, double* c2) {
-  const int n1 = I.n1, nn = I.ndof1;
+  const int n1 = I.n1;
   const G<double>* __restrict__ V = gp(I.V);
-  for (int o = threadIdx.x; o < nn; o += NT) {
-    const int k = o / n1, ix = o - k * n1;
-    double s = 0.0;
-#pragma unroll 8
-    for (int iy = 0; iy < n1; ++iy) s += V[iy * n1 + k] * c1[iy * n1 + ix];
-    c2[o] = s;
-  }
+  coarse_transform<NT, true>(n1, V, c1, c2);  // c2[k][ix] = sum_iy V[iy][k] c1[iy][ix]
   __syncthreads();
   for (int k = threadIdx.x; k < n1; k += NT) {
     // the coefficients are loaded 8 at a time so their latency is paid once per chunk, not per
@@ -440,14 +496,7 @@ __device__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, do
     }
   }
   __syncthreads();
-  for (int o = threadIdx.x; o < nn; o += NT) {
-    const int iy = o / n1, ix = o - iy * n1;
-    double s = 0.0;
-    const G<double>* __restrict__ Vr = V + iy * n1;
-#pragma unroll 8
-    for (int k = 0; k < n1; ++k) s += Vr[k] * c2[k * n1 + ix];
-    c1[o] = s;
-  }
+  coarse_transform<NT, false>(n1, V, c2, c1);  // c1[iy][ix] = sum_k V[iy][k] c2[k][ix]
   __syncthreads();
 }
 
