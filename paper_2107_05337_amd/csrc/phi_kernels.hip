@@ -89,33 +89,43 @@ __device__ __forceinline__ const G<float>* band_ptr<float>(const BandDev& B) {
 constexpr int kBandMax = 11;  // widest 1D band: 2p + 1 at p = 5
 
 // first-direction pass: T[r][o] = sum_d B[o][d] * in[r][o + lo + d] for r < nrows, o < B.rows
-// (in has nin columns; band entries outside the input range are zero, their index is clamped)
+// (in has nin columns; band entries outside the input range are zero, their index is clamped).
+// Thread (o, g) keeps band row o in registers and covers rows g, g + NT / nout, ...
 template <int NT, typename AT, typename IT, typename OT>
 __device__ __forceinline__ void pass_x(int nrows, int nin, const BandDev& Bd, const IT* in, OT* out) {
   const G<AT>* __restrict__ B = band_ptr<AT>(Bd);
   const int nout = Bd.rows, w = Bd.w, lo = Bd.lo;
+  if (w <= kBandMax && nout <= NT) {
+    const int groups = NT / nout;
+    const int o = threadIdx.x % nout, g = threadIdx.x / nout;
+    if (g >= groups) return;
+    AT b[kBandMax];
+    int jj[kBandMax];
+#pragma unroll
+    for (int d = 0; d < kBandMax; ++d) {
+      b[d] = d < w ? B[o * w + d] : (AT)0;
+      int j = o + lo + d;
+      jj[d] = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+    }
+    for (int r = g; r < nrows; r += groups) {
+      const IT* src = in + r * nin;
+      AT s = 0;
+#pragma unroll
+      for (int d = 0; d < kBandMax; ++d) s += b[d] * (AT)src[jj[d]];
+      out[r * nout + o] = (OT)s;
+    }
+    return;
+  }
   const int tot = nrows * nout;
   for (int t = threadIdx.x; t < tot; t += NT) {
     const int r = t / nout, o = t - r * nout;
     const IT* src = in + r * nin;
     const G<AT>* b = B + o * w;
-    // unrolled to the widest band of p <= 5 with clamped addresses, so every load of the output
-    // issues at once (wider bands take the loop)
     AT s = 0;
-    if (w <= kBandMax) {
-#pragma unroll
-      for (int d = 0; d < kBandMax; ++d) {
-        int j = o + lo + d;
-        j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
-        const AT bd = b[d < w ? d : w - 1];
-        s += (d < w ? bd : (AT)0) * (AT)src[j];
-      }
-    } else {
-      for (int d = 0; d < w; ++d) {
-        int j = o + lo + d;
-        j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
-        s += b[d] * (AT)src[j];
-      }
+    for (int d = 0; d < w; ++d) {
+      int j = o + lo + d;
+      j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+      s += b[d] * (AT)src[j];
     }
     out[t] = (OT)s;
   }
