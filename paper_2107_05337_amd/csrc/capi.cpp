@@ -749,6 +749,10 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
       for (int i = 0; i < H->ninst; ++i)
         if (mk[i] == want) G.inst.push_back(i);
       if (G.inst.empty()) continue;
+      // costliest instances first: workgroups are dispatched in job order, so when a sweep has
+      // more jobs than CUs the cheaper chains fill the later rounds
+      auto cost = [&](int i) { return (double)H->inst[i].ndof * (2 * H->inst[i].p + 1); };
+      std::stable_sort(G.inst.begin(), G.inst.end(), [&](int a, int b) { return cost(a) > cost(b); });
       for (int i : G.inst) {
         const InstHost& I = H->inst[i];
         G.nmax = std::max(G.nmax, I.ndof);
