@@ -9,11 +9,12 @@ MGRIT solve of all three instances from the zero initial iterate to the 1e-10 re
 
 Variants: plain FP64 V-cycles; FP32 V-cycles inside FP64 iterative refinement; "tuned":
 FP32-refined with the autotuned LDS placement, the HIP-graph-captured iteration and coarse-level
-spatial solves to 1e-6 (level 0 stays at 1e-12); and that with the learned warm start.  `value` is the fastest variant (all reach the same 1e-10 residual).  The network of the
-learned variant is trained first (not timed) on sequential solver trajectories of other sources.  The dominant kernel's
-roofline uses HIP events the library records around each of its launches on the solve stream
-(around each captured iteration in graph mode).  The CPU baseline times the oracle (single
-thread) on a bounded sample.
+spatial solves to 1e-4 (level 0 stays at 1e-12); and that with the learned warm start.
+`value` is the fastest variant (all reach the same 1e-10 residual).  The network of the learned
+variant is trained first (not timed) on sequential solver trajectories of other sources.  The
+dominant kernel's roofline uses HIP events the library records around each of its launches on
+the solve stream (around each captured iteration in graph mode).  The CPU baseline times the
+oracle (single thread) on a bounded sample.
 
 --c4: the learned-warm-start measurement at p = 3, h 2^-6, N_t 4096: a network trained on 64
 sequential trajectories (sources seeded 0..63), then sequential solves of four unseen sources
@@ -310,8 +311,8 @@ def main():
         print(json.dumps(net_bench()))
         return
     specs = {"fp64": dict(precision=0), "fp32": dict(precision=1),
-             "fp32+tuned": dict(precision=1, autotune=1, graph=1, coarse_tol=1e-6),
-             "fp32+learned": dict(precision=1, guess=3, autotune=1, graph=1, coarse_tol=1e-6)}
+             "fp32+tuned": dict(precision=1, autotune=1, graph=1, coarse_tol=1e-4),
+             "fp32+learned": dict(precision=1, guess=3, autotune=1, graph=1, coarse_tol=1e-4)}
     variants = {}
     finals = {}
     for v in args.variants.split(","):
