@@ -261,17 +261,23 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* 
   const bool slot = r < R;
   // wavefronts whose row slots are all empty issue no loads (a wave-uniform branch)
   const bool wave_live = (int)((threadIdx.x & ~63) / TG) < R;
+  // the record is loaded by lane 0 of the quad only and broadcast to the quad when used (a level
+  // later, when the load has arrived)
   auto load_meta = [&](int l, Meta4& m) {
-    if (!wave_live) {
-      m = Meta4{-1, 0, 0, V};
-      return;
-    }
+    m = Meta4{-1, 0, 0, V};
+    if (!wave_live || g != 0) return;
     const I4 v = meta[slot ? 1 + l * R + r : 0];
     m = Meta4{v.x, v.y, v.z, v.w};
   };
+  auto bcast = [&](Meta4& m) {
+    m.row = __builtin_amdgcn_mov_dpp(m.row, 0x00, 0xF, 0xF, true);  // quad_perm [0, 0, 0, 0]
+    m.bo = __builtin_amdgcn_mov_dpp(m.bo, 0x00, 0xF, 0xF, true);
+    m.bq0 = __builtin_amdgcn_mov_dpp(m.bq0, 0x00, 0xF, 0xF, true);
+    m.bc = __builtin_amdgcn_mov_dpp(m.bc, 0x00, 0xF, 0xF, true);
+  };
   // off-block rows: a zero row at 0, slot (l, r) at RW + (l * R + r) * RW
-  auto load_a = [&](int l, VT* av, int* ac) {
-    if (!wave_live) {
+  auto load_a = [&](int l, VT* av, int* ac, bool live) {
+    if (!wave_live || !live) {  // empty slots: zero coefficients on a valid column
 #pragma unroll
       for (int j = 0; j < KA; ++j) {
         av[j] = (VT)0;
@@ -299,11 +305,13 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* 
 #pragma unroll
       for (int e = 0; e < V; ++e) bv[k * V + e] = v[e];
     }
-    const int xi = m.row >= 0 ? m.row : 0;
-    if constexpr (IN_GLOBAL)
-      xin = gp(in_g)[xi];
-    else
-      xin = ((const L3<VT>*)in_g)[xi];
+    xin = (VT)0;  // only lane 0 of the quad writes the row's result
+    if (g == 0 && m.row >= 0) {
+      if constexpr (IN_GLOBAL)
+        xin = gp(in_g)[m.row];
+      else
+        xin = ((const L3<VT>*)in_g)[m.row];
+    }
   };
   auto phase_a = [&](const VT* av, const int* ac, int row, VT xin) {
     VT s = 0;
@@ -330,14 +338,16 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* 
   Meta4 M0, M1;
   load_meta(0, M0);
   load_meta(1, M1);
-  load_a(0, av, ac);
+  bcast(M0);
+  load_a(0, av, ac, M0.row >= 0);
   load_b(M0, bv0, x0);
   for (int l = 0; l < nlev; l += 2) {
     {  // even level l
       const Meta4 m = M0;
       phase_a(av, ac, m.row, x0);
       lds_barrier();
-      load_a(l + 1, av, ac);
+      bcast(M1);
+      load_a(l + 1, av, ac, M1.row >= 0);
       load_b(M1, bv1, x1);
       load_meta(l + 2, M0);
       phase_b(bv0, m);
@@ -348,7 +358,8 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* 
       const Meta4 m = M1;
       phase_a(av, ac, m.row, x1);
       lds_barrier();
-      load_a(l + 2, av, ac);
+      bcast(M0);
+      load_a(l + 2, av, ac, M0.row >= 0);
       load_b(M0, bv0, x0);
       load_meta(l + 3, M1);
       phase_b(bv1, m);
