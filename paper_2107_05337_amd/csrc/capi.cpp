@@ -480,13 +480,15 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
   T.bs = S.bs;
   T.max_rows = S.max_rows;
   // the prefetched register path holds one row per 8 lanes (128 rows per level), up to 64
-  // off-block entries per row and dense rows of up to 72 entries
+  // off-block entries per row and dense rows of up to 72 entries starting below word 65536
   int maxo = 0, maxd = 0;
   for (size_t q = 0; q + 1 < S.orp.size(); ++q) maxo = std::max(maxo, S.orp[q + 1] - S.orp[q]);
   for (int c : S.dcnt) maxd = std::max(maxd, c);
+  int maxq = 0;  // the dense start column travels in 16 bits of the slot metadata
+  for (int c : S.dq0) maxq = std::max(maxq, c);
   const size_t aslots = ((size_t)S.nlev * std::max(1, S.max_rows) + 1) * (size_t)RW;
   T.fast = (zidx >= 0 && S.max_rows <= kRowSlots && maxo <= RW && maxo <= kOffMax && maxd <= kDenseMax &&
-            S.dval.size() + 1 < (size_t)INT32_MAX && aslots < (size_t)INT32_MAX)
+            maxq < 65536 && S.dval.size() + 1 < (size_t)INT32_MAX && aslots < (size_t)INT32_MAX)
                ? 1
                : 0;
   int* p;
@@ -525,7 +527,7 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
     std::vector<int> acol(aslots, zidx);
     std::vector<double> aval(aslots, 0.0);
     std::vector<double> dfast((size_t)TGh * V, 0.0);  // a zero row of one vector per lane at 0
-    meta[0] = Meta4{-1, 0, 0, V};
+    meta[0] = Meta4{-1, 0, V << 16, 0};
     for (int l = 0; l < S.nlev; ++l)
       for (int q = S.lev_ptr[l]; q < S.lev_ptr[l + 1]; ++q) {
         const int r = q - S.lev_ptr[l];
@@ -537,7 +539,7 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
         if (bo + (size_t)TGh * bc >= (size_t)INT32_MAX) return fail(PMGRIT_E_OOM, "dense table too large");
         dfast.resize(bo + (size_t)TGh * bc, 0.0);
         for (int c = 0; c < S.dcnt[q]; ++c) dfast[bo + lead + c] = S.dval[S.doff[q] + c];
-        meta[1 + sl] = Meta4{S.row[q], (int)bo, q0, bc};
+        meta[1 + sl] = Meta4{S.row[q], (int)bo, q0 | (bc << 16), na};
         for (int t = 0; t < na; ++t) {
           aval[(1 + sl) * AS + t] = S.ov[S.orp[q] + t];
           acol[(1 + sl) * AS + t] = S.oci[S.orp[q] + t];

@@ -15,10 +15,11 @@ constexpr int kDenseMax = 72;
 // per (level, row slot) metadata of the prefetched triangular solve
 struct Meta4 {
   int row;   // row (or -1 for an empty slot)
-  int bo;    // offset of the row's dense chunks in dfast (a multiple of 16 bytes)
-  int bq0;   // s position of the first dense column (a multiple of 16 bytes' worth of values)
-  int bc;    // dense values per lane: the row holds 4 bc values (units of 16 bytes, lane g
-             // reading units g, g + 4, ...)
+  int bo;    // offset of the row's dense values in dfast (a multiple of 16 bytes)
+  int bqc;   // s position of the first dense column (low 16 bits, a multiple of 16 bytes' worth of
+             // values) | dense values per lane << 16 (the row holds 4 x that many, lane g reading
+             // 16-byte units g, g + 4, ...)
+  int na;    // off-block entries of the row (the rest of its AS-wide row is padding)
 };
 
 // level-scheduled blocked triangular solve (see TriSchedule in host_setup.hpp)

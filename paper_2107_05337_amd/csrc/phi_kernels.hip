@@ -246,7 +246,8 @@ __device__ __forceinline__ T quad_sum(T v) {
 }
 
 template <typename VT, bool IN_GLOBAL, int KA>
-__device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* in_g, L3<VT>* y, L3<VT>* sbuf) {
+__device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, const VT* in_g, L3<VT>* y,
+                                       L3<VT>* sbuf) {
   constexpr int TG = Cfg<VT>::TG, RW = KA * TG, V = 16 / (int)sizeof(VT), BCM = 20;
   constexpr int WA = KA < V ? KA : V;  // off-block unit width
   typedef VT VV __attribute__((ext_vector_type(V)));
@@ -264,7 +265,7 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* 
   // the record is loaded by lane 0 of the quad only and broadcast to the quad when used (a level
   // later, when the load has arrived)
   auto load_meta = [&](int l, Meta4& m) {
-    m = Meta4{-1, 0, 0, V};
+    m = Meta4{-1, 0, V << 16, 0};
     if (!wave_live || g != 0) return;
     const I4 v = meta[slot ? 1 + l * R + r : 0];
     m = Meta4{v.x, v.y, v.z, v.w};
@@ -272,23 +273,38 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* 
   auto bcast = [&](Meta4& m) {
     m.row = __builtin_amdgcn_mov_dpp(m.row, 0x00, 0xF, 0xF, true);  // quad_perm [0, 0, 0, 0]
     m.bo = __builtin_amdgcn_mov_dpp(m.bo, 0x00, 0xF, 0xF, true);
-    m.bq0 = __builtin_amdgcn_mov_dpp(m.bq0, 0x00, 0xF, 0xF, true);
-    m.bc = __builtin_amdgcn_mov_dpp(m.bc, 0x00, 0xF, 0xF, true);
+    m.bqc = __builtin_amdgcn_mov_dpp(m.bqc, 0x00, 0xF, 0xF, true);
+    m.na = __builtin_amdgcn_mov_dpp(m.na, 0x00, 0xF, 0xF, true);
   };
   // off-block rows: a zero row at 0, slot (l, r) at RW + (l * R + r) * RW
-  auto load_a = [&](int l, VT* av, int* ac, bool live) {
-    if (!wave_live || !live) {  // empty slots: zero coefficients on a valid column
+  // off-block row: lane g loads units g, g + 4, ... of WA entries.  In FP64 (two entries per
+  // unit) only the units that hold entries (na) are loaded, the rest being zero coefficients on
+  // the always-zero LDS word; in FP32 the whole padded row of a live slot is loaded (fewer, wider
+  // units: the per-unit selects would cost more than the loads they save)
+  auto load_a = [&](int l, VT* av, int* ac, int na) {
 #pragma unroll
-      for (int j = 0; j < KA; ++j) {
-        av[j] = (VT)0;
-        ac[j] = 0;
-      }
-      return;
+    for (int j = 0; j < KA; ++j) {
+      av[j] = (VT)0;
+      ac[j] = zidx;
     }
+    if (!wave_live || na <= 0) return;
     const int base = (slot && l < nlev) ? RW + (l * R + r) * RW : 0;
-    qload<VT, KA, WA>(aval + base, g, av);
-    qload<int, KA, WA>(acol + base, g, ac);
+    typedef VT VW __attribute__((ext_vector_type(WA)));
+    typedef int IW __attribute__((ext_vector_type(WA)));
+#pragma unroll
+    for (int k = 0; k < KA / WA; ++k) {
+      if (sizeof(VT) == 4 || (k * 4 + g) * WA < na) {
+        const VW v = ((const G<VW>*)(aval + base))[k * 4 + g];
+        const IW c = ((const G<IW>*)(acol + base))[k * 4 + g];
+#pragma unroll
+        for (int e = 0; e < WA; ++e) {
+          av[k * WA + e] = v[e];
+          ac[k * WA + e] = c[e];
+        }
+      }
+    }
   };
+
   // dense row: this lane's units g, g + 4, ... (bc values in all; zeros past them)
   auto load_b = [&](const Meta4& m, VT* bv, VT& xin) {
     if (!wave_live) {
@@ -298,10 +314,11 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* 
       return;
     }
     const G<VV>* src = (const G<VV>*)(dv + m.bo);
+    const int bc = m.bqc >> 16;
 #pragma unroll
     for (int k = 0; k < BCM / V; ++k) {
       VV v = {};
-      if (k * V < m.bc) v = src[k * 4 + g];
+      if (k * V < bc) v = src[k * 4 + g];
 #pragma unroll
       for (int e = 0; e < V; ++e) bv[k * V + e] = v[e];
     }
@@ -323,7 +340,7 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* 
   // padding carries zero coefficients; sbuf beyond the level's rows holds finite values
   auto phase_b = [&](const VT* bv, const Meta4& m) {
     VT s = 0;
-    const L3<VV>* sp = (const L3<VV>*)(sbuf + m.bq0);
+    const L3<VV>* sp = (const L3<VV>*)(sbuf + (m.bqc & 0xffff));
 #pragma unroll
     for (int k = 0; k < BCM / V; ++k) {
       const VV sv = sp[k * 4 + g];
@@ -339,7 +356,7 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* 
   load_meta(0, M0);
   load_meta(1, M1);
   bcast(M0);
-  load_a(0, av, ac, M0.row >= 0);
+  load_a(0, av, ac, M0.na);
   load_b(M0, bv0, x0);
   for (int l = 0; l < nlev; l += 2) {
     {  // even level l
@@ -347,7 +364,7 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* 
       phase_a(av, ac, m.row, x0);
       lds_barrier();
       bcast(M1);
-      load_a(l + 1, av, ac, M1.row >= 0);
+      load_a(l + 1, av, ac, M1.na);
       load_b(M1, bv1, x1);
       load_meta(l + 2, M0);
       phase_b(bv0, m);
@@ -359,7 +376,7 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, const VT* 
       phase_a(av, ac, m.row, x1);
       lds_barrier();
       bcast(M0);
-      load_a(l + 2, av, ac, M0.row >= 0);
+      load_a(l + 2, av, ac, M0.na);
       load_b(M0, bv0, x0);
       load_meta(l + 3, M1);
       phase_b(bv1, m);
@@ -406,20 +423,20 @@ __device__ void trsv_general(const TriDev& T, const VT* in, VT* y, VT* sbuf) {
 }
 
 template <typename VT, bool YLDS, bool IN_GLOBAL>
-__device__ __forceinline__ void trsv(const TriDev& T, int ka, const VT* in, VT* y, VT* sbuf) {
+__device__ __forceinline__ void trsv(const TriDev& T, int ka, int zidx, const VT* in, VT* y, VT* sbuf) {
   if (YLDS && T.fast) {
     L3<VT>* yl = (L3<VT>*)y;
     L3<VT>* sl = (L3<VT>*)sbuf;
     if (ka <= 2)
-      trsv_fast<VT, IN_GLOBAL, 2>(&T, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 2>(&T, zidx, in, yl, sl);
     else if (ka <= 4)
-      trsv_fast<VT, IN_GLOBAL, 4>(&T, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 4>(&T, zidx, in, yl, sl);
     else if (ka <= 8)
-      trsv_fast<VT, IN_GLOBAL, 8>(&T, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 8>(&T, zidx, in, yl, sl);
     else if (ka <= 12)
-      trsv_fast<VT, IN_GLOBAL, 12>(&T, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 12>(&T, zidx, in, yl, sl);
     else
-      trsv_fast<VT, IN_GLOBAL, 16>(&T, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 16>(&T, zidx, in, yl, sl);
   } else {
     trsv_general<VT>(T, in, y, sbuf);
   }
@@ -526,19 +543,19 @@ __device__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, do
 // Buffers: y (nin^2 doubles, LDS first), s (>= max(nin^2 VT, n1^2 doubles)), d (nin^2 VT).
 template <typename VT, int MASK>
 __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, const VT* r, VT* d, VT* y, VT* s,
-                       VT* sbuf, int ka) {
+                       VT* sbuf, int ka, int zidx) {
   constexpr bool YL = MASK & kY;
   constexpr int NT = Cfg<VT>::NT;
   const int n = I.ndof;
   // step 1: pre-smoothing d = S r, then nu1 - 1 further steps d += S (r - A d)
-  trsv<VT, YL, true>(L.L, ka, r, y, sbuf);
-  trsv<VT, YL, !YL>(L.U, ka, y, y, sbuf);
+  trsv<VT, YL, true>(L.L, ka, zidx, r, y, sbuf);
+  trsv<VT, YL, !YL>(L.U, ka, zidx, y, y, sbuf);
   for (int i = threadIdx.x; i < n; i += NT) d[i] = y[i];
   __syncthreads();
   for (int m = 1; m < nu1; ++m) {
     apply_A<NT, VT>(I, L, d, r, s, y);
-    trsv<VT, YL, !(MASK & kS)>(L.L, ka, s, y, sbuf);
-    trsv<VT, YL, !YL>(L.U, ka, y, y, sbuf);
+    trsv<VT, YL, !(MASK & kS)>(L.L, ka, zidx, s, y, sbuf);
+    trsv<VT, YL, !YL>(L.U, ka, zidx, y, y, sbuf);
     for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
     __syncthreads();
   }
@@ -560,8 +577,8 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
   // step 5: nu2 post-smoothing steps d += S (r - A d)
   for (int m = 0; m < nu2; ++m) {
     apply_A<NT, VT>(I, L, d, r, s, y);
-    trsv<VT, YL, !(MASK & kS)>(L.L, ka, s, y, sbuf);
-    trsv<VT, YL, !YL>(L.U, ka, y, y, sbuf);
+    trsv<VT, YL, !(MASK & kS)>(L.L, ka, zidx, s, y, sbuf);
+    trsv<VT, YL, !YL>(L.U, ka, zidx, y, y, sbuf);
     for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
     __syncthreads();
   }
@@ -661,7 +678,7 @@ __global__ void __launch_bounds__(Cfg<VT>::NT) phi_kernel(PhiParams P, LdsPlan p
         if (threadIdx.x == 0) atomicOr(P.status, 2);
         break;
       }
-      vcycle<VT, MASK>(I, L, P.nu1, P.nu2, r, d, y, s, sbuf, plan.ka);
+      vcycle<VT, MASK>(I, L, P.nu1, P.nu2, r, d, y, s, sbuf, plan.ka, plan.zidx);
       for (int i = threadIdx.x; i < n; i += NT) x[i] += (double)d[i];
       __syncthreads();
       ++cyc;
