@@ -83,7 +83,7 @@ def train_network(n_src: int = 4, epochs: int = 8, batch: int = 64, lr: float = 
 
 
 def unit_bytes(S, inst: int, precision: int) -> float:
-    """Algorithmic bytes of one V-cycle on one right-hand side (see DESIGN.md): the vector traffic
+    """Algorithmic bytes of one V-cycle on one right-hand side: the vector traffic
     of an unfused V-cycle, 26 n_dof + 6 n_dof1 words, plus the matrices one V-cycle streams
     (A three times, the ILUT factors L and U twice, P twice, the p = 1 fast-diagonalisation data
     twice) amortised over the 128 right-hand sides of a level-0 F-sweep."""
@@ -155,7 +155,9 @@ def cpu_baseline(iters: int):
     est = dt * (iters + 1) / 2.0
     return dict(value=d["Nt"] / est, unit="time-step solves/s", cores=1, kind="oracle",
                 sample=f"oracle MGRIT on {WORKLOAD[0]} (single thread), max_iter=1 timed {dt:.1f} s, "
-                       f"scaled by (iters+1)/2 with iters={iters} to a full 1e-10 solve; rc={r['rc']}")
+                       f"scaled by (iters+1)/2 with iters={iters} to a full 1e-10 solve (p=3 is the cheapest "
+                       f"instance of the workload, so this over-states the oracle's rate on it); "
+                       f"return code {r['rc']} = stopped at max_iter, as the sample intends")
 
 
 def traffic_for(kernel_src_hash: str):
