@@ -488,7 +488,7 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
   for (int c : S.dq0) maxq = std::max(maxq, c);
   const size_t aslots = ((size_t)S.nlev * std::max(1, S.max_rows) + 1) * (size_t)RW;
   T.fast = (zidx >= 0 && S.max_rows <= kRowSlots && maxo <= RW && maxo <= kOffMax && maxd <= kDenseMax &&
-            maxq < 65536 && S.dval.size() + 1 < (size_t)INT32_MAX && aslots < (size_t)INT32_MAX)
+            maxq < 65536 && S.dval.size() + 1 < (size_t)INT32_MAX && aslots * sizeof(double) < (size_t)kBufBytes)
                ? 1
                : 0;
   int* p;
@@ -524,10 +524,10 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
     const int V = H->fp32 ? 4 : 2;  // values per 16 bytes
     const size_t nslots = (size_t)(S.nlev + 2) * R + 1;
     std::vector<Meta4> meta(nslots, Meta4{-1, 0, 0, 0});
-    std::vector<int> acol(aslots, zidx);
+    std::vector<int> acol(aslots, 0);  // columns relative to the zero word zidx (padding: 0)
     std::vector<double> aval(aslots, 0.0);
     std::vector<double> dfast((size_t)TGh * V, 0.0);  // a zero row of one vector per lane at 0
-    meta[0] = Meta4{-1, 0, V << 16, 0};
+    meta[0] = Meta4{-1, 0, 0, 0};
     for (int l = 0; l < S.nlev; ++l)
       for (int q = S.lev_ptr[l]; q < S.lev_ptr[l + 1]; ++q) {
         const int r = q - S.lev_ptr[l];
@@ -536,13 +536,14 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
         const int q0 = S.dq0[q] / V * V, lead = S.dq0[q] - q0, cnt = S.dcnt[q] + lead;
         const int bc = (cnt + TGh * V - 1) / (TGh * V) * V;
         const size_t bo = dfast.size();
-        if (bo + (size_t)TGh * bc >= (size_t)INT32_MAX) return fail(PMGRIT_E_OOM, "dense table too large");
+        if ((bo + (size_t)TGh * bc) * sizeof(double) >= (size_t)kBufBytes)
+          return fail(PMGRIT_E_OOM, "dense table too large");
         dfast.resize(bo + (size_t)TGh * bc, 0.0);
         for (int c = 0; c < S.dcnt[q]; ++c) dfast[bo + lead + c] = S.dval[S.doff[q] + c];
         meta[1 + sl] = Meta4{S.row[q], (int)bo, q0 | (bc << 16), na};
         for (int t = 0; t < na; ++t) {
           aval[(1 + sl) * AS + t] = S.ov[S.orp[q] + t];
-          acol[(1 + sl) * AS + t] = S.oci[S.orp[q] + t];
+          acol[(1 + sl) * AS + t] = S.oci[S.orp[q] + t] - zidx;
         }
       }
     T.R = R;

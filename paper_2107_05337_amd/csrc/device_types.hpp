@@ -10,6 +10,9 @@ constexpr int kMaxLevels = 12;   // MGRIT time levels per instance
 // slots per level, up to 64 off-block entries per row and dense diagonal blocks of up to 72 rows.
 constexpr int kRowSlots = 128;
 constexpr int kOffMax = 64;
+// the prefetched triangular solve reads its slot tables through buffer descriptors of this many
+// bytes (every table of that path is smaller); an offset at or past it reads zeros
+constexpr unsigned kBufBytes = 0x7ffff000u;
 constexpr int kDenseMax = 72;
 
 // per (level, row slot) metadata of the prefetched triangular solve
@@ -31,7 +34,8 @@ struct TriDev {
   const Meta4* meta;             // [1 + (nlev + 2) * R]
   const void* dfast;             // dense rows, natural column order, 4 * Meta4::bc values each
   const void* aval;              // [(1 + nlev * R) * AS] off-block values, row 0 = padding
-  const int* acol;               // [(1 + nlev * R) * AS] off-block columns (padding: the zero word)
+  const int* acol;               // [(1 + nlev * R) * AS] off-block columns minus the zero word's
+                                 // index (padding: 0, i.e. the zero word)
   // general path: level-ordered CSR
   const int* lev_ptr;
   const int* row;

@@ -245,30 +245,78 @@ __device__ __forceinline__ T quad_sum(T v) {
   return v;
 }
 
+// buffer descriptor over a table of the prefetched solve (raw, stride 0, kBufBytes long):
+// a load at an offset of kBufBytes or more returns zeros without touching memory
+// (the pointer is wave-uniform; reading it from the first lane puts the descriptor in scalar
+// registers, as buffer instructions need)
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const unsigned long long a = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+  return (T*)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(const_cast<void*>(p)), (short)0, (int)kBufBytes, 0x00020000);
+}
+constexpr int kOff = (int)0x80000000u;  // an offset past every table: the load returns zeros
+
+template <int BYTES>
+__device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t rs, int off, unsigned* out) {
+  if constexpr (BYTES == 16) {
+    typedef unsigned U4 __attribute__((ext_vector_type(4)));
+    const U4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    out[0] = v.x, out[1] = v.y, out[2] = v.z, out[3] = v.w;
+  } else if constexpr (BYTES == 8) {
+    typedef unsigned U2 __attribute__((ext_vector_type(2)));
+    const U2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+    out[0] = v.x, out[1] = v.y;
+  } else {
+    static_assert(BYTES == 4, "unit size");
+    out[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+  }
+}
+
+// Prefetched blocked triangular solve (one workgroup, 4 lanes per row, up to kRowSlots rows per
+// level).  Per level: phase A forms s_i = in_i - sum of the row's off-block entries times y
+// (finished levels), phase B multiplies s by the row's part of the dense diagonal-block inverse.
+// The tables of level l + 1 stream in while level l computes: its dense rows (and the slot
+// metadata of level l + 2) are requested before phase A of level l, its off-block rows right
+// after phase A.  Every table load is a buffer load whose unused lanes take an offset past the
+// table (zeros, no memory traffic), so the loop has no divergent branches and a fixed number of
+// loads in flight, and each wait covers only the data about to be used.  Off-block columns are
+// stored relative to the zero word zidx, so a zeroed unit is a zero coefficient on that word.
 template <typename VT, bool IN_GLOBAL, int KA>
 __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, const VT* in_g, L3<VT>* y,
                                        L3<VT>* sbuf) {
   constexpr int TG = Cfg<VT>::TG, RW = KA * TG, V = 16 / (int)sizeof(VT), BCM = 20;
-  constexpr int WA = KA < V ? KA : V;  // off-block unit width
+  constexpr int WA = KA < V ? KA : V;  // off-block entries per unit
+  constexpr int NU = KA / WA;          // off-block units per lane
+  constexpr int ND = BCM / V;          // dense units per lane
+  constexpr int VB = (int)sizeof(VT);
   typedef VT VV __attribute__((ext_vector_type(V)));
-  typedef int I4 __attribute__((ext_vector_type(4)));
   static_assert(TG == 4, "quad sums assume 4 lanes per row");
-  const G<VT>* __restrict__ aval = gp((const VT*)Tp->aval);
-  const G<int>* __restrict__ acol = gp(Tp->acol);
-  const G<VT>* __restrict__ dv = gp((const VT*)Tp->dfast);
-  const G<I4>* __restrict__ meta = (const G<I4>*)gp(Tp->meta);
-  const int R = Tp->R, nlev = Tp->nlev;
+  Tp = uniform_ptr(Tp);  // the schedule header is the same for the whole workgroup
+  const __amdgpu_buffer_rsrc_t rval = table_rsrc(Tp->aval), rcol = table_rsrc(Tp->acol),
+                               rden = table_rsrc(Tp->dfast), rmeta = table_rsrc(Tp->meta),
+                               rin = table_rsrc(in_g);
+  const int R = __builtin_amdgcn_readfirstlane(Tp->R), nlev = __builtin_amdgcn_readfirstlane(Tp->nlev);
   const int r = threadIdx.x / TG, g = threadIdx.x & (TG - 1);
   const bool slot = r < R;
-  // wavefronts whose row slots are all empty issue no loads (a wave-uniform branch)
-  const bool wave_live = (int)((threadIdx.x & ~63) / TG) < R;
-  // the record is loaded by lane 0 of the quad only and broadcast to the quad when used (a level
-  // later, when the load has arrived)
+  const L3<VT>* yz = y + __builtin_amdgcn_readfirstlane(zidx);
+  if ((int)((threadIdx.x & ~63) / TG) >= R) {
+    // a wavefront whose row slots are all empty only keeps the barriers of the level loop
+    for (int l = 0; l < nlev; ++l) {
+      lds_barrier();
+      lds_barrier();
+    }
+    return;
+  }
+  // slot metadata: loaded by lane 0 of the quad, broadcast to the quad when its level comes
   auto load_meta = [&](int l, Meta4& m) {
-    m = Meta4{-1, 0, V << 16, 0};
-    if (!wave_live || g != 0) return;
-    const I4 v = meta[slot ? 1 + l * R + r : 0];
-    m = Meta4{v.x, v.y, v.z, v.w};
+    unsigned u[4];
+    buf_load<16>(rmeta, g == 0 ? (slot ? 1 + l * R + r : 0) * 16 : kOff, u);
+    m = Meta4{(int)u[0], (int)u[1], (int)u[2], (int)u[3]};
   };
   auto bcast = [&](Meta4& m) {
     m.row = __builtin_amdgcn_mov_dpp(m.row, 0x00, 0xF, 0xF, true);  // quad_perm [0, 0, 0, 0]
@@ -276,73 +324,68 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
     m.bqc = __builtin_amdgcn_mov_dpp(m.bqc, 0x00, 0xF, 0xF, true);
     m.na = __builtin_amdgcn_mov_dpp(m.na, 0x00, 0xF, 0xF, true);
   };
-  // off-block rows: a zero row at 0, slot (l, r) at RW + (l * R + r) * RW
-  // off-block row: lane g loads units g, g + 4, ... of WA entries.  In FP64 (two entries per
-  // unit) only the units that hold entries (na) are loaded, the rest being zero coefficients on
-  // the always-zero LDS word; in FP32 the whole padded row of a live slot is loaded (fewer, wider
-  // units: the per-unit selects would cost more than the loads they save)
-  auto load_a = [&](int l, VT* av, int* ac, int na) {
+  // off-block row of slot (l, r) at RW + (l * R + r) * RW: lane g reads units g, g + 4, ... of
+  // WA entries, those past the row's na entries read as zeros
+  auto load_a = [&](int l, const Meta4& m, VT* av, int* ac) {
+    const int base = RW + (l * R + r) * RW;
 #pragma unroll
-    for (int j = 0; j < KA; ++j) {
-      av[j] = (VT)0;
-      ac[j] = zidx;
-    }
-    if (!wave_live || na <= 0) return;
-    const int base = (slot && l < nlev) ? RW + (l * R + r) * RW : 0;
-    typedef VT VW __attribute__((ext_vector_type(WA)));
-    typedef int IW __attribute__((ext_vector_type(WA)));
+    for (int k = 0; k < NU; ++k) {
+      const int e0 = (k * 4 + g) * WA;
+      const bool live = e0 < m.na;
+      unsigned uv[WA * VB / 4], uc[WA];
+      buf_load<WA * VB>(rval, live ? (base + e0) * VB : kOff, uv);
+      buf_load<WA * 4>(rcol, live ? (base + e0) * 4 : kOff, uc);
 #pragma unroll
-    for (int k = 0; k < KA / WA; ++k) {
-      if (sizeof(VT) == 4 || (k * 4 + g) * WA < na) {
-        const VW v = ((const G<VW>*)(aval + base))[k * 4 + g];
-        const IW c = ((const G<IW>*)(acol + base))[k * 4 + g];
-#pragma unroll
-        for (int e = 0; e < WA; ++e) {
-          av[k * WA + e] = v[e];
-          ac[k * WA + e] = c[e];
-        }
+      for (int e = 0; e < WA; ++e) {
+        if constexpr (VB == 8)
+          av[k * WA + e] = __builtin_bit_cast(double, ((unsigned long long)uv[2 * e + 1] << 32) | uv[2 * e]);
+        else
+          av[k * WA + e] = __builtin_bit_cast(float, uv[e]);
+        ac[k * WA + e] = (int)uc[e];
       }
     }
   };
-
-  // dense row: this lane's units g, g + 4, ... (bc values in all; zeros past them)
+  // dense row at m.bo: lane g reads units g, g + 4, ... (bc values per lane, zeros past them),
+  // and lane 0 of the quad the row's right-hand side
   auto load_b = [&](const Meta4& m, VT* bv, VT& xin) {
-    if (!wave_live) {
-#pragma unroll
-      for (int j = 0; j < BCM; ++j) bv[j] = (VT)0;
-      xin = (VT)0;
-      return;
-    }
-    const G<VV>* src = (const G<VV>*)(dv + m.bo);
     const int bc = m.bqc >> 16;
 #pragma unroll
-    for (int k = 0; k < BCM / V; ++k) {
-      VV v = {};
-      if (k * V < bc) v = src[k * 4 + g];
+    for (int k = 0; k < ND; ++k) {
+      unsigned u[4];
+      buf_load<16>(rden, k * V < bc ? (m.bo + (k * 4 + g) * V) * VB : kOff, u);
 #pragma unroll
-      for (int e = 0; e < V; ++e) bv[k * V + e] = v[e];
+      for (int e = 0; e < V; ++e) {
+        if constexpr (VB == 8)
+          bv[k * V + e] = __builtin_bit_cast(double, ((unsigned long long)u[2 * e + 1] << 32) | u[2 * e]);
+        else
+          bv[k * V + e] = __builtin_bit_cast(float, u[e]);
+      }
     }
-    xin = (VT)0;  // only lane 0 of the quad writes the row's result
-    if (g == 0 && m.row >= 0) {
-      if constexpr (IN_GLOBAL)
-        xin = gp(in_g)[m.row];
+    const bool own = g == 0 && m.row >= 0;
+    if constexpr (IN_GLOBAL) {
+      unsigned u[VB / 4];
+      buf_load<VB>(rin, own ? m.row * VB : kOff, u);
+      if constexpr (VB == 8)
+        xin = __builtin_bit_cast(double, ((unsigned long long)u[1] << 32) | u[0]);
       else
-        xin = ((const L3<VT>*)in_g)[m.row];
+        xin = __builtin_bit_cast(float, u[0]);
+    } else {
+      xin = ((const L3<VT>*)in_g)[own ? m.row : 0];
     }
   };
   auto phase_a = [&](const VT* av, const int* ac, int row, VT xin) {
     VT s = 0;
 #pragma unroll
-    for (int j = 0; j < KA; ++j) s += av[j] * y[ac[j]];
+    for (int j = 0; j < KA; ++j) s += av[j] * yz[ac[j]];
     s = quad_sum(s);
     if (g == 0 && row >= 0) sbuf[r] = xin - s;
   };
-  // padding carries zero coefficients; sbuf beyond the level's rows holds finite values
+  // sbuf beyond the level's rows holds finite values, met by zero coefficients
   auto phase_b = [&](const VT* bv, const Meta4& m) {
     VT s = 0;
     const L3<VV>* sp = (const L3<VV>*)(sbuf + (m.bqc & 0xffff));
 #pragma unroll
-    for (int k = 0; k < BCM / V; ++k) {
+    for (int k = 0; k < ND; ++k) {
       const VV sv = sp[k * 4 + g];
 #pragma unroll
       for (int e = 0; e < V; ++e) s += bv[k * V + e] * sv[e];
@@ -355,30 +398,35 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
   Meta4 M0, M1;
   load_meta(0, M0);
   load_meta(1, M1);
+  // keep the prologue's loads in this order: the loop head waits for M1 with the off-block
+  // loads of its level still in flight, on entry as on every later iteration
+  __builtin_amdgcn_sched_barrier(0);
   bcast(M0);
-  load_a(0, av, ac, M0.na);
   load_b(M0, bv0, x0);
+  __builtin_amdgcn_sched_barrier(0);
+  load_a(0, M0, av, ac);
+  __builtin_amdgcn_sched_barrier(0);
   for (int l = 0; l < nlev; l += 2) {
-    {  // even level l
+    {  // even level l: M0 (broadcast), bv0, x0 and av/ac hold its data; M1 is level l + 1's
       const Meta4 m = M0;
-      phase_a(av, ac, m.row, x0);
-      lds_barrier();
       bcast(M1);
-      load_a(l + 1, av, ac, M1.na);
       load_b(M1, bv1, x1);
       load_meta(l + 2, M0);
+      phase_a(av, ac, m.row, x0);
+      lds_barrier();
+      load_a(l + 1, M1, av, ac);
       phase_b(bv0, m);
       lds_barrier();
     }
     if (l + 1 >= nlev) break;
     {  // odd level l + 1
       const Meta4 m = M1;
-      phase_a(av, ac, m.row, x1);
-      lds_barrier();
       bcast(M0);
-      load_a(l + 2, av, ac, M0.na);
       load_b(M0, bv0, x0);
       load_meta(l + 3, M1);
+      phase_a(av, ac, m.row, x1);
+      lds_barrier();
+      load_a(l + 2, M0, av, ac);
       phase_b(bv1, m);
       lds_barrier();
     }
