@@ -191,40 +191,11 @@ __device__ double apply_A(const InstDev& I, const LevelDev& L, const XT* x, cons
 // blocked level-scheduled triangular solves
 // ---------------------------------------------------------------------------------------
 
-// Prefetched path: T y = in (T = L with unit diagonal, or U), solution written to y (which may
-// alias in).  Thread (r, g) = (row slot tid / TG, lane tid % TG).  Per level: phase A forms
-// s_r = in_i - sum_{off-block j} T_ij y_j, phase B multiplies each block's s by its dense
-// diagonal-block inverse.  The schedule is stored as slot tables whose addresses follow from
-// (level, slot, lane): off-block rows are exactly KA * TG entries wide, padded with zero values
-// whose column is an LDS word y[zidx] that holds 0 (row 0 is all padding, for empty slots), so
-// every lane runs the same branch-free code.  Entry 0 of the metadata and dense tables is a
-// reserved empty / zero entry.  The level
-// loop is unrolled by two with ping-pong registers: the metadata of level l+2 and the data of
-// level l+1 are issued while level l computes, and no register is copied while its load is in
-// flight.  y and sbuf are LDS, the barriers fence LDS only, and the function is kept out of line
-// so its registers are allocated on their own.
+// Both paths solve T y = in (T = L with unit diagonal, or U), writing y (which may alias in),
+// level by level over a blocked level schedule (blocks = grid lines, split to at most
+// kDenseMax rows; a level is a set of independent blocks).
 template <class T>
 using L3 = __attribute__((address_space(3))) T;
-
-// loads of N values of a row as units of W consecutive values, lane g of the row's quad taking
-// units g, g + 4, g + 8, ...: one instruction reads 4 W contiguous values per row (p must be
-// aligned to W values)
-template <class T, int N, int W>
-__device__ __forceinline__ void qload(const G<T>* p, int g, T* out) {
-  static_assert(N % W == 0, "whole units");
-  if constexpr (W > 1) {
-    typedef T VW __attribute__((ext_vector_type(W)));
-#pragma unroll
-    for (int k = 0; k < N / W; ++k) {
-      const VW v = ((const G<VW>*)p)[k * 4 + g];
-#pragma unroll
-      for (int e = 0; e < W; ++e) out[k * W + e] = v[e];
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < N; ++k) out[k] = p[k * 4 + g];
-  }
-}
 
 // sum over the 4 lanes of a quad with DPP lane permutes (no LDS round trip)
 template <int CTRL>
@@ -280,9 +251,10 @@ __device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t rs, int off, uns
 // Prefetched blocked triangular solve (one workgroup, 4 lanes per row, up to kRowSlots rows per
 // level).  Per level: phase A forms s_i = in_i - sum of the row's off-block entries times y
 // (finished levels), phase B multiplies s by the row's part of the dense diagonal-block inverse.
-// The tables of level l + 1 stream in while level l computes: its dense rows (and the slot
-// metadata of level l + 2) are requested before phase A of level l, its off-block rows right
-// after phase A.  Every table load is a buffer load whose unused lanes take an offset past the
+// The tables of level l + 1 stream in while level l computes: its off-block rows are requested
+// right after phase A of level l, its dense rows (and the slot metadata of level l + 2) right
+// after phase B (FP32) or before phase A (FP64), so the loads overlap the barriers and the
+// other phase.  Every table load is a buffer load whose unused lanes take an offset past the
 // table (zeros, no memory traffic), so the loop has no divergent branches and a fixed number of
 // loads in flight, and each wait covers only the data about to be used.  Off-block columns are
 // stored relative to the zero word zidx, so a zeroed unit is a zero coefficient on that word.
@@ -348,6 +320,18 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
   // dense row at m.bo: lane g reads units g, g + 4, ... (bc values per lane, zeros past them),
   // and lane 0 of the quad the row's right-hand side
   auto load_b = [&](const Meta4& m, VT* bv, VT& xin) {
+    // the right-hand side first: phase A needs it before phase B needs the dense row
+    const bool own = g == 0 && m.row >= 0;
+    if constexpr (IN_GLOBAL) {
+      unsigned u[VB / 4];
+      buf_load<VB>(rin, own ? m.row * VB : kOff, u);
+      if constexpr (VB == 8)
+        xin = __builtin_bit_cast(double, ((unsigned long long)u[1] << 32) | u[0]);
+      else
+        xin = __builtin_bit_cast(float, u[0]);
+    } else {
+      xin = ((const L3<VT>*)in_g)[own ? m.row : 0];
+    }
     const int bc = m.bqc >> 16;
 #pragma unroll
     for (int k = 0; k < ND; ++k) {
@@ -360,17 +344,6 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
         else
           bv[k * V + e] = __builtin_bit_cast(float, u[e]);
       }
-    }
-    const bool own = g == 0 && m.row >= 0;
-    if constexpr (IN_GLOBAL) {
-      unsigned u[VB / 4];
-      buf_load<VB>(rin, own ? m.row * VB : kOff, u);
-      if constexpr (VB == 8)
-        xin = __builtin_bit_cast(double, ((unsigned long long)u[1] << 32) | u[0]);
-      else
-        xin = __builtin_bit_cast(float, u[0]);
-    } else {
-      xin = ((const L3<VT>*)in_g)[own ? m.row : 0];
     }
   };
   auto phase_a = [&](const VT* av, const int* ac, int row, VT xin) {
@@ -393,42 +366,78 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
     s = quad_sum(s);
     if (g == 0 && m.row >= 0) y[m.row] = s;
   };
-  VT av[KA], bv0[BCM], bv1[BCM], x0, x1;
-  int ac[KA];
-  Meta4 M0, M1;
-  load_meta(0, M0);
-  load_meta(1, M1);
-  // keep the prologue's loads in this order: the loop head waits for M1 with the off-block
-  // loads of its level still in flight, on entry as on every later iteration
-  __builtin_amdgcn_sched_barrier(0);
-  bcast(M0);
-  load_b(M0, bv0, x0);
-  __builtin_amdgcn_sched_barrier(0);
-  load_a(0, M0, av, ac);
-  __builtin_amdgcn_sched_barrier(0);
-  for (int l = 0; l < nlev; l += 2) {
-    {  // even level l: M0 (broadcast), bv0, x0 and av/ac hold its data; M1 is level l + 1's
-      const Meta4 m = M0;
-      bcast(M1);
-      load_b(M1, bv1, x1);
-      load_meta(l + 2, M0);
-      phase_a(av, ac, m.row, x0);
+  if constexpr (sizeof(VT) == 4) {
+    // FP32 (one buffer per table).  Level l starts with its off-block rows (av, ac), dense row
+    // (bv, xin) and broadcast metadata (C) loaded or in flight, and level l + 1's metadata record
+    // in N.  Level l + 1's off-block rows are requested after phase A of level l, its dense row
+    // after phase B; the scheduling barriers keep those requests where they are, so that each
+    // wait covers only the data about to be used.
+    VT av[KA], bv[BCM], xin;
+    int ac[KA];
+    Meta4 C, N;
+    load_meta(0, C);
+    load_meta(1, N);
+    __builtin_amdgcn_sched_barrier(0);
+    bcast(C);
+    load_a(0, C, av, ac);
+    __builtin_amdgcn_sched_barrier(0);
+    load_b(C, bv, xin);
+    __builtin_amdgcn_sched_barrier(0);
+    for (int l = 0; l < nlev; ++l) {
+      phase_a(av, ac, C.row, xin);
+      __builtin_amdgcn_sched_barrier(0);
+      bcast(N);
+      load_a(l + 1, N, av, ac);
       lds_barrier();
-      load_a(l + 1, M1, av, ac);
-      phase_b(bv0, m);
+      phase_b(bv, C);
+      __builtin_amdgcn_sched_barrier(0);
+      Meta4 N2;
+      load_meta(l + 2, N2);
+      load_b(N, bv, xin);
+      C = N;
+      N = N2;
       lds_barrier();
     }
-    if (l + 1 >= nlev) break;
-    {  // odd level l + 1
-      const Meta4 m = M1;
-      bcast(M0);
-      load_b(M0, bv0, x0);
-      load_meta(l + 3, M1);
-      phase_a(av, ac, m.row, x1);
-      lds_barrier();
-      load_a(l + 2, M0, av, ac);
-      phase_b(bv1, m);
-      lds_barrier();
+  } else {
+    // FP64 (dense rows twice as wide: two dense buffers, so that the next level's dense row
+    // streams in during phase A rather than holding up the barrier after phase B).  The loop is
+    // unrolled by two: at even level l, M0 (broadcast), bv0, x0 and av/ac hold its data and M1
+    // level l + 1's metadata record.
+    VT av[KA], bv0[BCM], bv1[BCM], x0, x1;
+    int ac[KA];
+    Meta4 M0, M1;
+    load_meta(0, M0);
+    load_meta(1, M1);
+    __builtin_amdgcn_sched_barrier(0);
+    bcast(M0);
+    load_b(M0, bv0, x0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_a(0, M0, av, ac);
+    __builtin_amdgcn_sched_barrier(0);
+    for (int l = 0; l < nlev; l += 2) {
+      {  // even level l
+        const Meta4 m = M0;
+        bcast(M1);
+        load_b(M1, bv1, x1);
+        load_meta(l + 2, M0);
+        phase_a(av, ac, m.row, x0);
+        lds_barrier();
+        load_a(l + 1, M1, av, ac);
+        phase_b(bv0, m);
+        lds_barrier();
+      }
+      if (l + 1 >= nlev) break;
+      {  // odd level l + 1
+        const Meta4 m = M1;
+        bcast(M0);
+        load_b(M0, bv0, x0);
+        load_meta(l + 3, M1);
+        phase_a(av, ac, m.row, x1);
+        lds_barrier();
+        load_a(l + 2, M0, av, ac);
+        phase_b(bv1, m);
+        lds_barrier();
+      }
     }
   }
 }
