@@ -131,7 +131,8 @@ def run_variant(precision: int, steps: int, warmup: int, guess: int = 2, autotun
     res = dict(value=nsteps_total / sec_per_step, ms_per_step=1e3 * sec_per_step,
                mgrit_iters=stats[-1]["mgrit_iters"], vcycles_per_solve=stats[-1]["vcycles"],
                phi_calls=stats[-1]["phi_calls"], kernel_ms=prof["ms"], launches=prof["launches"],
-               unit_bytes=ubar, units=prof["vcycles"], lds_masks=[S.group_info(i)["lds_mask"] for i in range(S.n)])
+               unit_bytes=ubar, units=prof["vcycles"], lds_masks=[S.group_info(i)["lds_mask"] for i in range(S.n)],
+               lds_masks_wide=[S.group_info(i)["lds_mask_wide"] for i in range(S.n)])
     final = [o.clone() for o in outs]
     S.close()
     return res, final

@@ -103,10 +103,18 @@ typedef struct {
   int32_t guess;          /* 0 zero, 1 previous, 2 current target, 3 learned */
   int32_t trsv_block;     /* see above */
   int32_t autotune;       /* 1: at create, time candidate LDS placements of the work vectors per
-                           * launch group on probe solves and keep the fastest */
+                           * launch group on probe solves and keep the fastest (in precision 1
+                           * also the two-workgroups-per-CU build where the plan fits half of
+                           * the CU's LDS) */
   double coarse_tol;      /* spatial tolerance of the solves on MGRIT levels >= 1 (0: spatial_tol);
                            * those only supply corrections, so it changes the convergence rate,
                            * not the fixed point that the level-0 stop test measures */
+  int32_t lds_mask;       /* 0: automatic (the largest LDS placement that fits, or the autotuner's
+                           * choice).  Otherwise the placement of every launch group: bits 1 y,
+                           * 2 d, 4 s, 8 x select the work vectors kept in LDS; 16 (precision 1
+                           * with bit 1 and without 4 and 8) selects the kernel build for two
+                           * workgroups per CU.  Results do not depend on it.  PMGRIT_E_ARG if it
+                           * does not fit a group's LDS or is combined with autotune. */
 } pmgrit_solver_opts;
 
 typedef struct {
@@ -261,9 +269,11 @@ pmgrit_status pmgrit_info(const pmgrit_handle* h, int64_t* out8);
 
 /* Launch group of an instance.  Instances are grouped by the LDS placement their sizes allow;
  * each group launches with its own configuration on its own stream, forked from and joined
- * back into the caller's stream at every sweep.  out8 = {group id, number of groups, LDS mask,
- * dynamic LDS bytes, off-block entries per lane of the triangular solves, instances in the
- * group, largest dof count in the group, workgroup slots}.  Errors: PMGRIT_E_ARG for a bad
+ * back into the caller's stream at every sweep.  out8 = {group id, number of groups, LDS mask
+ * of the sweeps with at most as many workgroups as the device has CUs | LDS mask of the wider
+ * sweeps << 8 (masks as in pmgrit_solver_opts.lds_mask), dynamic LDS bytes of the first,
+ * off-block entries per lane of the triangular solves, instances in the group, largest dof
+ * count in the group, workgroup slots}.  Errors: PMGRIT_E_ARG for a bad
  * instance or NULL out8, PMGRIT_E_STATE for a host-only handle. */
 pmgrit_status pmgrit_group_info(const pmgrit_handle* h, int32_t inst, int64_t* out8);
 

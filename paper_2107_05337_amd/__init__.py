@@ -39,7 +39,7 @@ class SolverOpts(C.Structure):
     _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("ilut_droptol", C.c_double), ("ilut_fill", C.c_int32),
                 ("spatial_tol", C.c_double), ("max_vcycles", C.c_int32), ("precision", C.c_int32),
                 ("guess", C.c_int32), ("trsv_block", C.c_int32), ("autotune", C.c_int32),
-                ("coarse_tol", C.c_double)]
+                ("coarse_tol", C.c_double), ("lds_mask", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -140,7 +140,7 @@ def _dptr(t):
 
 def default_solver_opts(**kw) -> SolverOpts:
     o = SolverOpts(nu1=1, nu2=1, ilut_droptol=1e-12, ilut_fill=0, spatial_tol=1e-12, max_vcycles=100, precision=0,
-                   guess=2, trsv_block=-1, autotune=0, coarse_tol=0.0)
+                   guess=2, trsv_block=-1, autotune=0, coarse_tol=0.0, lds_mask=0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -192,11 +192,15 @@ class Solver:
         return dict(zip(keys, list(out)))
 
     def group_info(self, inst: int = 0):
-        """Launch group of instance inst: dict(group, groups, lds_mask, lds_bytes, ka, size, nmax, slots)."""
+        """Launch group of instance inst: dict(group, groups, lds_mask, lds_mask_wide, lds_bytes, ka,
+        size, nmax, slots); lds_mask_wide is the placement of sweeps wider than the device's CUs."""
         out = (C.c_int64 * 8)()
         _check(lib().pmgrit_group_info(self._h, inst, out))
         keys = ["group", "groups", "lds_mask", "lds_bytes", "ka", "size", "nmax", "slots"]
-        return dict(zip(keys, list(out)))
+        d = dict(zip(keys, list(out)))
+        d["lds_mask_wide"] = d["lds_mask"] >> 8
+        d["lds_mask"] &= 0xFF
+        return d
 
     def profile(self, enable: int = -1):
         """Live kernel timing: enable 1 resets and starts, 0 stops, -1 only reads.  Returns

@@ -75,6 +75,7 @@ struct DevBuf {
 
 struct pmgrit_handle {
   int device = -1;
+  int ncu = 256;  // compute units of the device (sweeps wider than this use the wide placement)
   int ninst = 0;
   pmgrit_mgrit_opts mo{};
   pmgrit_solver_opts so{};
@@ -108,6 +109,10 @@ struct pmgrit_handle {
     int mask = 0, lds_bytes = 0, nmax = 0, n1max = 0, ka = 2, rw = 8, maxrows = 1;
     float tuned_ms = 0.f;  // probe time of the chosen placement (autotune)
     LdsPlan plan{-1, -1, -1, -1, 512, 0, 0, 2};
+    // placement of the sweeps with more workgroups than the device has CUs (the level-0 sweeps),
+    // where two workgroups per CU can pay; mask / lds_bytes / plan serve the narrower ones
+    int wmask = 0, wbytes = 0;
+    LdsPlan wplan{-1, -1, -1, -1, 512, 0, 0, 2};
     std::vector<JobList> jF, jC, jRES;  // per level: F-relaxation chains, C-steps, C-point residuals
     JobList jCoarsest, jSeq;
     // single-step lists of the learned warm start: level-0 F steps per position s in the
@@ -737,6 +742,7 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
   const int vt = H->fp32 ? 4 : 8;
   int dev_lds = 0;
   HIPCHK(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, H->device));
+  HIPCHK(hipDeviceGetAttribute(&H->ncu, hipDeviceAttributeMultiprocessorCount, H->device));
   // group the instances by the LDS placement each would get on its own
   H->inst_group.assign(H->ninst, -1);
   {
@@ -771,6 +777,17 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
       }
       G.rw = G.ka * 4;
       lds_plan(G.nmax, G.n1max, G.maxrows, vt, G.ka, dev_lds, G.mask, G.lds_bytes, G.plan);
+      if (H->so.lds_mask) {  // placement chosen by the caller
+        int bytes = 0;
+        const LdsPlan plan = lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, G.ka, dev_lds, H->so.lds_mask, bytes);
+        if (bytes == 0) return fail(PMGRIT_E_ARG, "lds_mask does not fit a launch group's LDS");
+        G.mask = H->so.lds_mask;
+        G.lds_bytes = bytes;
+        G.plan = plan;
+      }
+      G.wmask = G.mask;
+      G.wbytes = G.lds_bytes;
+      G.wplan = G.plan;
       for (int i : G.inst) H->inst_group[i] = (int)H->groups.size();
       H->groups.push_back(std::move(G));
     }
@@ -897,6 +914,7 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
     HIPCHK(hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&G.done, hipEventDisableTiming));
     HIPCHK(phi_prepare(H->fp32, G.mask, G.lds_bytes));
+    HIPCHK(phi_prepare(H->fp32, G.wmask, G.wbytes));
   }
   TRY(learned_setup(H));
   HIPCHK(hipEventCreateWithFlags(&H->fork, hipEventDisableTiming));
@@ -956,7 +974,10 @@ static hipError_t phi_timed(pmgrit_handle* H, const pmgrit_handle::Group& G, con
                             hipStream_t st) {
   H->nlaunch_total++;
   H->nwg_total += nblocks;
-  if (!H->prof) return phi_launch(H->fp32, G.mask, G.lds_bytes, P, G.plan, nblocks, st);
+  const bool wide = nblocks > H->ncu;
+  const int mask = wide ? G.wmask : G.mask, bytes = wide ? G.wbytes : G.lds_bytes;
+  const LdsPlan& plan = wide ? G.wplan : G.plan;
+  if (!H->prof) return phi_launch(H->fp32, mask, bytes, P, plan, nblocks, st);
   hipError_t e;
   if (H->ev_used * 2 + 2 > (int)H->ev.size()) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
@@ -964,7 +985,7 @@ static hipError_t phi_timed(pmgrit_handle* H, const pmgrit_handle::Group& G, con
   }
   const int k = H->ev_used++;
   if ((e = hipEventRecord(H->ev[2 * k], st)) != hipSuccess) return e;
-  if ((e = phi_launch(H->fp32, G.mask, G.lds_bytes, P, G.plan, nblocks, st)) != hipSuccess) return e;
+  if ((e = phi_launch(H->fp32, mask, bytes, P, plan, nblocks, st)) != hipSuccess) return e;
   H->prof_launches++;
   H->prof_wgs += nblocks;
   return hipEventRecord(H->ev[2 * k + 1], st);
@@ -1115,7 +1136,11 @@ static pmgrit_status autotune(pmgrit_handle* H) {
     if (!(G.mask & kY)) continue;  // placements without y in LDS use the general solve
     const int inst = G.inst[0];
     const int nd = H->inst[inst].ndof;
-    const int nrhs = std::max(1, std::min(kGivenMax, G.jF.empty() ? 64 : std::max(G.jF[0].n, 64)));
+    // two probes: as wide as a level-0 sweep (the wide placement) and as narrow as a level-1
+    // sweep (the placement of every narrower launch)
+    const int nwide = std::max(1, std::min(kGivenMax, G.jF.empty() ? 64 : std::max(G.jF[0].n, 64)));
+    const int nnarrow = std::max(1, std::min(H->ncu, G.jF.size() > 1 ? std::max(G.jF[1].n, 1) : 8));
+    const int nrhs = std::max(nwide, nnarrow);
     std::vector<double> hb((size_t)nrhs * nd);
     uint64_t z = 0x2545F4914F6CDD1Dull;
     for (double& v : hb) {  // a fixed pseudo-random right-hand side (xorshift64)
@@ -1133,45 +1158,60 @@ static pmgrit_status autotune(pmgrit_handle* H) {
     for (int j = 0; j < nrhs; ++j) H->h_given_jobs[j] = PhiJob{inst, 0, 0, 1, 0, 0};
     HIPCHK(hipMemcpy(G.d_given_jobs, H->h_given_jobs, sizeof(PhiJob) * nrhs, hipMemcpyHostToDevice));
     H->given_key[0] = -1;
-    const int keep_mask = G.mask, keep_bytes = G.lds_bytes;
-    const LdsPlan keep_plan = G.plan;
-    int best_mask = keep_mask, best_bytes = keep_bytes;
-    LdsPlan best_plan = keep_plan;
-    float best_ms = 1e30f;
-    for (int mk : {15, 7, 3, 1}) {
-      int bytes = 0;
-      const LdsPlan plan = lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, G.ka, dev_lds, mk, bytes);
-      if (bytes == 0) continue;
-      HIPCHK(phi_prepare(H->fp32, mk, bytes));
-      G.mask = mk;
-      G.lds_bytes = bytes;
-      G.plan = plan;
-      PhiParams P = base_params(H, G, kModeGiven, G.d_given_jobs);
-      P.vtab = nullptr;
-      P.bgiven = b;
-      P.xgiven = x;
-      P.guess = 0;
-      float ms = 0.f;
-      for (int rep = 0; rep < 2; ++rep) {
-        HIPCHK(hipMemset(x, 0, sizeof(double) * hb.size()));
-        HIPCHK(hipEventRecord(e0, nullptr));
-        HIPCHK(phi_launch(H->fp32, mk, bytes, P, plan, nrhs, nullptr));
-        HIPCHK(hipEventRecord(e1, nullptr));
-        HIPCHK(hipEventSynchronize(e1));
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    // fastest placement for a probe of n right-hand sides
+    auto probe = [&](int n, int& best_mask, int& best_bytes, LdsPlan& best_plan, float& best_ms) -> hipError_t {
+      best_ms = 1e30f;
+      for (int mk : {15, 7, 3, 1, 3 | kOcc2, 1 | kOcc2}) {
+        if ((mk & kOcc2) && !H->fp32) continue;
+        int bytes = 0;
+        const LdsPlan plan = lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, G.ka, dev_lds, mk, bytes);
+        if (bytes == 0 || ((mk & kOcc2) && 2 * bytes > dev_lds)) continue;
+        hipError_t e = phi_prepare(H->fp32, mk, bytes);
+        if (e != hipSuccess) return e;
+        G.mask = mk;
+        G.lds_bytes = bytes;
+        G.plan = plan;
+        PhiParams P = base_params(H, G, kModeGiven, G.d_given_jobs);
+        P.vtab = nullptr;
+        P.bgiven = b;
+        P.xgiven = x;
+        P.guess = 0;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+          if ((e = hipMemset(x, 0, sizeof(double) * hb.size())) != hipSuccess) return e;
+          if ((e = hipEventRecord(e0, nullptr)) != hipSuccess) return e;
+          if ((e = phi_launch(H->fp32, mk, bytes, P, plan, n, nullptr)) != hipSuccess) return e;
+          if ((e = hipEventRecord(e1, nullptr)) != hipSuccess) return e;
+          if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+          if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return e;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_mask = mk;
+          best_bytes = bytes;
+          best_plan = plan;
+        }
       }
-      if (ms < best_ms) {
-        best_ms = ms;
-        best_mask = mk;
-        best_bytes = bytes;
-        best_plan = plan;
-      }
+      return hipSuccess;
+    };
+    int nm = G.mask, nb = G.lds_bytes, wm = G.mask, wb = G.lds_bytes;
+    LdsPlan np = G.plan, wp = G.plan;
+    float nms = 0.f, wms = 0.f;
+    HIPCHK(probe(nnarrow, nm, nb, np, nms));
+    if (nwide > H->ncu) {
+      HIPCHK(probe(nwide, wm, wb, wp, wms));
+    } else {
+      wm = nm, wb = nb, wp = np, wms = nms;
     }
-    G.mask = best_mask;
-    G.lds_bytes = best_bytes;
-    G.plan = best_plan;
-    G.tuned_ms = best_ms;
+    G.mask = nm;
+    G.lds_bytes = nb;
+    G.plan = np;
+    G.wmask = wm;
+    G.wbytes = wb;
+    G.wplan = wp;
+    G.tuned_ms = nms;
     HIPCHK(phi_prepare(H->fp32, G.mask, G.lds_bytes));
+    HIPCHK(phi_prepare(H->fp32, G.wmask, G.wbytes));
   }
   HIPCHK(hipEventDestroy(e0));
   HIPCHK(hipEventDestroy(e1));
@@ -1195,7 +1235,10 @@ pmgrit_status pmgrit_create(int32_t n_instances, const pmgrit_problem* probs, co
     return fail(PMGRIT_E_ARG, "invalid MGRIT options");
   if (so.nu1 < 1 || so.nu2 < 0 || !(so.ilut_droptol >= 0) || !(so.spatial_tol > 0) || so.max_vcycles < 1 ||
       (so.precision != 0 && so.precision != 1) || so.guess < 0 || so.guess > 3 || so.trsv_block < -1 ||
-      so.autotune < 0 || so.autotune > 1 || !(so.coarse_tol >= 0) || so.coarse_tol >= 1)
+      so.autotune < 0 || so.autotune > 1 || !(so.coarse_tol >= 0) || so.coarse_tol >= 1 || so.lds_mask < 0 ||
+      so.lds_mask > 31 || (so.lds_mask && so.autotune) ||
+      ((so.lds_mask & kOcc2) && (so.precision != 1 || (so.lds_mask & 15) != ((so.lds_mask & 15) & (kY | kD)) ||
+                                 !(so.lds_mask & kY))))
     return fail(PMGRIT_E_ARG, "invalid solver options");
   for (int i = 0; i < n_instances; ++i) {
     const pmgrit_problem& p = probs[i];
@@ -1734,7 +1777,7 @@ pmgrit_status pmgrit_group_info(const pmgrit_handle* h, int32_t inst, int64_t* o
   const pmgrit_handle::Group& G = h->groups[h->inst_group[inst]];
   out8[0] = h->inst_group[inst];
   out8[1] = (int64_t)h->groups.size();
-  out8[2] = G.mask;
+  out8[2] = G.mask | (G.wmask << 8);
   out8[3] = G.lds_bytes;
   out8[4] = G.ka;
   out8[5] = (int64_t)G.inst.size();

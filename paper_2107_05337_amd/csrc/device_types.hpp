@@ -120,5 +120,8 @@ struct LdsPlan {
 };
 
 enum : int { kY = 1, kD = 2, kS = 4, kX = 8 };
+// placement flag: the FP32 spatial-solve kernel built for two 512-thread workgroups per CU (at
+// most 128 VGPRs per lane); with an LDS plan of at most half the CU's LDS two chains then share a CU
+constexpr int kOcc2 = 16;
 
 }  // namespace pmg

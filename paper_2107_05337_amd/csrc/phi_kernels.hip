@@ -173,7 +173,9 @@ __device__ __forceinline__ double pass_y(int ncols, int nin, const BandDev& Bd, 
 
 // out = beta z - A_l x with A_l = My (x) X1 + c Ky (x) Mx2 (temp: nin x nin scratch, may not
 // alias x or out).  Returns this thread's share of ||out||^2.
-template <int NT, typename AT, typename XT, typename ZT, typename OT, typename TT>
+// (OCC only separates the instances called from the two-workgroups-per-CU kernels, which get
+// their register budget)
+template <int NT, typename AT, int OCC = 1, typename XT, typename ZT, typename OT, typename TT>
 __device__ double apply_A(const InstDev& I, const LevelDev& L, const XT* x, const ZT* z, OT* out, TT* tmp) {
   const int n = I.nin;
   pass_x<NT, AT>(n, n, L.X1, x, tmp);
@@ -258,7 +260,7 @@ __device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t rs, int off, uns
 // table (zeros, no memory traffic), so the loop has no divergent branches and a fixed number of
 // loads in flight, and each wait covers only the data about to be used.  Off-block columns are
 // stored relative to the zero word zidx, so a zeroed unit is a zero coefficient on that word.
-template <typename VT, bool IN_GLOBAL, int KA>
+template <typename VT, bool IN_GLOBAL, int KA, int OCC>
 __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, const VT* in_g, L3<VT>* y,
                                        L3<VT>* sbuf) {
   constexpr int TG = Cfg<VT>::TG, RW = KA * TG, V = 16 / (int)sizeof(VT), BCM = 20;
@@ -479,21 +481,21 @@ __device__ void trsv_general(const TriDev& T, const VT* in, VT* y, VT* sbuf) {
   }
 }
 
-template <typename VT, bool YLDS, bool IN_GLOBAL>
+template <typename VT, bool YLDS, bool IN_GLOBAL, int OCC>
 __device__ __forceinline__ void trsv(const TriDev& T, int ka, int zidx, const VT* in, VT* y, VT* sbuf) {
   if (YLDS && T.fast) {
     L3<VT>* yl = (L3<VT>*)y;
     L3<VT>* sl = (L3<VT>*)sbuf;
     if (ka <= 2)
-      trsv_fast<VT, IN_GLOBAL, 2>(&T, zidx, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 2, OCC>(&T, zidx, in, yl, sl);
     else if (ka <= 4)
-      trsv_fast<VT, IN_GLOBAL, 4>(&T, zidx, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 4, OCC>(&T, zidx, in, yl, sl);
     else if (ka <= 8)
-      trsv_fast<VT, IN_GLOBAL, 8>(&T, zidx, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 8, OCC>(&T, zidx, in, yl, sl);
     else if (ka <= 12)
-      trsv_fast<VT, IN_GLOBAL, 12>(&T, zidx, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 12, OCC>(&T, zidx, in, yl, sl);
     else
-      trsv_fast<VT, IN_GLOBAL, 16>(&T, zidx, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 16, OCC>(&T, zidx, in, yl, sl);
   } else {
     trsv_general<VT>(T, in, y, sbuf);
   }
@@ -598,26 +600,26 @@ __device__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, do
 // one p-multigrid V-cycle from the zero guess on A d = r (Sec. 4, steps 1-5, in correction
 // form: the outer FP64 loop supplies r = b - A x and adds d to x).
 // Buffers: y (nin^2 doubles, LDS first), s (>= max(nin^2 VT, n1^2 doubles)), d (nin^2 VT).
-template <typename VT, int MASK>
+template <typename VT, int MASK, int OCC>
 __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, const VT* r, VT* d, VT* y, VT* s,
                        VT* sbuf, int ka, int zidx) {
   constexpr bool YL = MASK & kY;
   constexpr int NT = Cfg<VT>::NT;
   const int n = I.ndof;
   // step 1: pre-smoothing d = S r, then nu1 - 1 further steps d += S (r - A d)
-  trsv<VT, YL, true>(L.L, ka, zidx, r, y, sbuf);
-  trsv<VT, YL, !YL>(L.U, ka, zidx, y, y, sbuf);
+  trsv<VT, YL, true, OCC>(L.L, ka, zidx, r, y, sbuf);
+  trsv<VT, YL, !YL, OCC>(L.U, ka, zidx, y, y, sbuf);
   for (int i = threadIdx.x; i < n; i += NT) d[i] = y[i];
   __syncthreads();
   for (int m = 1; m < nu1; ++m) {
-    apply_A<NT, VT>(I, L, d, r, s, y);
-    trsv<VT, YL, !(MASK & kS)>(L.L, ka, zidx, s, y, sbuf);
-    trsv<VT, YL, !YL>(L.U, ka, zidx, y, y, sbuf);
+    apply_A<NT, VT, OCC>(I, L, d, r, s, y);
+    trsv<VT, YL, !(MASK & kS), OCC>(L.L, ka, zidx, s, y, sbuf);
+    trsv<VT, YL, !YL, OCC>(L.U, ka, zidx, y, y, sbuf);
     for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
     __syncthreads();
   }
   // step 2: residual restricted to p = 1, r1 = (M1^L)^{-1} P^T (r - A d); r1 lands in s
-  apply_A<NT, VT>(I, L, d, r, s, y);
+  apply_A<NT, VT, OCC>(I, L, d, r, s, y);
   double* c1 = (double*)s;
   double* c2 = (double*)y;
   pass_x<NT, VT>(I.nin, I.nin, I.PxT, s, y);  // nin rows x n1 columns
@@ -633,16 +635,16 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
   __syncthreads();
   // step 5: nu2 post-smoothing steps d += S (r - A d)
   for (int m = 0; m < nu2; ++m) {
-    apply_A<NT, VT>(I, L, d, r, s, y);
-    trsv<VT, YL, !(MASK & kS)>(L.L, ka, zidx, s, y, sbuf);
-    trsv<VT, YL, !YL>(L.U, ka, zidx, y, y, sbuf);
+    apply_A<NT, VT, OCC>(I, L, d, r, s, y);
+    trsv<VT, YL, !(MASK & kS), OCC>(L.L, ka, zidx, s, y, sbuf);
+    trsv<VT, YL, !YL, OCC>(L.U, ka, zidx, y, y, sbuf);
     for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
     __syncthreads();
   }
 }
 
-template <typename VT, int MASK>
-__global__ void __launch_bounds__(Cfg<VT>::NT) phi_kernel(PhiParams P, LdsPlan plan) {
+template <typename VT, int MASK, int OCC>
+__device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan) {
   constexpr int NT = Cfg<VT>::NT;
   extern __shared__ __align__(16) unsigned char smem[];
   const PhiJob job = P.jobs[blockIdx.x];
@@ -699,8 +701,8 @@ __global__ void __launch_bounds__(Cfg<VT>::NT) phi_kernel(PhiParams P, LdsPlan p
       if (P.guess == 4 && job.level == 0) {
         __syncthreads();
         double* rt = sizeof(VT) == 8 ? (double*)r : (double*)(ws + 5 * nm);  // FP64 residual temp
-        const double ra = block_sum<NT>(apply_A<NT, double>(I, L, x, b, rt, yd), red);
-        const double rp = block_sum<NT>(apply_A<NT, double>(I, L, vk, b, rt, yd), red);
+        const double ra = block_sum<NT>(apply_A<NT, double, OCC>(I, L, x, b, rt, yd), red);
+        const double rp = block_sum<NT>(apply_A<NT, double, OCC>(I, L, vk, b, rt, yd), red);
         if (!(ra <= rp))
           for (int i = threadIdx.x; i < n; i += NT) x[i] = vk[i];
       }
@@ -718,11 +720,11 @@ __global__ void __launch_bounds__(Cfg<VT>::NT) phi_kernel(PhiParams P, LdsPlan p
       // FP64 residual r = b - A x (stored in the V-cycle precision) and its norm
       part = 0.0;
       if constexpr (sizeof(VT) == 8) {
-        part = apply_A<NT, double>(I, L, x, b, r, yd);
+        part = apply_A<NT, double, OCC>(I, L, x, b, r, yd);
       } else {
         // residual in FP64 through the FP64 temp, then rounded into r
         double* rr = (double*)(ws + 5 * nm);  // FP64 residual staging in global scratch
-        part = apply_A<NT, double>(I, L, x, b, rr, yd);
+        part = apply_A<NT, double, OCC>(I, L, x, b, rr, yd);
         for (int i = threadIdx.x; i < n; i += NT) r[i] = (VT)rr[i];
       }
       const double rn2 = block_sum<NT>(part, red);
@@ -735,7 +737,7 @@ __global__ void __launch_bounds__(Cfg<VT>::NT) phi_kernel(PhiParams P, LdsPlan p
         if (threadIdx.x == 0) atomicOr(P.status, 2);
         break;
       }
-      vcycle<VT, MASK>(I, L, P.nu1, P.nu2, r, d, y, s, sbuf, plan.ka, plan.zidx);
+      vcycle<VT, MASK, OCC>(I, L, P.nu1, P.nu2, r, d, y, s, sbuf, plan.ka, plan.zidx);
       for (int i = threadIdx.x; i < n; i += NT) x[i] += (double)d[i];
       __syncthreads();
       ++cyc;
@@ -813,11 +815,27 @@ __global__ void norm_reduce_kernel(const double* __restrict__ nrm2, const int* _
 // host-side launch helpers (called from the driver)
 // ------------------------------------------------------------------------------------------
 
+// one workgroup per job; phi_kernel_o2 is the same code limited to 128 VGPRs per lane, so that
+// two workgroups fit a CU when the LDS plan leaves room for them
+template <typename VT, int MASK>
+__global__ void __launch_bounds__(Cfg<VT>::NT) phi_kernel(PhiParams P, LdsPlan plan) {
+  phi_body<VT, MASK, 1>(P, plan);
+}
+template <typename VT, int MASK>
+__global__ void __launch_bounds__(Cfg<VT>::NT) __attribute__((amdgpu_waves_per_eu(4))) phi_kernel_o2(PhiParams P,
+                                                                                                 LdsPlan plan) {
+  phi_body<VT, MASK, 2>(P, plan);
+}
+
 using PhiFn = void (*)(PhiParams, LdsPlan);
 
 template <typename VT>
 static PhiFn pick(int mask) {
-  switch (mask) {
+  if constexpr (sizeof(VT) == 4) {
+    if (mask == (3 | kOcc2)) return phi_kernel_o2<VT, 3>;
+    if (mask == (1 | kOcc2)) return phi_kernel_o2<VT, 1>;
+  }
+  switch (mask & 15) {
     case 15: return phi_kernel<VT, 15>;
     case 7: return phi_kernel<VT, 7>;
     case 3: return phi_kernel<VT, 3>;
@@ -826,9 +844,17 @@ static PhiFn pick(int mask) {
   }
 }
 
+// allow the kernel of a placement the device's whole per-workgroup LDS: several plans (wide and
+// narrow placements, launch groups, autotuner probes) may share one kernel, and each launch
+// requests its own plan's size (occupancy follows the launch's request, not this limit)
 hipError_t phi_prepare(int fp32, int mask, int lds_bytes) {
   PhiFn f = fp32 ? pick<float>(mask) : pick<double>(mask);
-  return hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  int dev = 0, mx = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  if (lds_bytes > mx) return hipErrorInvalidValue;
+  return hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
 }
 
 hipError_t phi_launch(int fp32, int mask, int lds_bytes, const PhiParams& P, const LdsPlan& plan, int nblocks,

@@ -34,13 +34,14 @@ def torch():
     return T
 
 
-def make_solver(cfg, precision=0, guess=2, trsv_block=-1, tol=1e-10, stol=1e-12, autotune=0, ctol=0.0, **mo):
+def make_solver(cfg, precision=0, guess=2, trsv_block=-1, tol=1e-10, stol=1e-12, autotune=0, ctol=0.0, lds_mask=0,
+                **mo):
     probs = [pm.problem(d["p"], d["n"], d["Nt"], kappa=d["kappa"], T=d["T"], domain=d["domain"])
              for d in cfg["instances"]]
     mopts = pm.default_mgrit_opts(cfactor=cfg["m"], max_levels=cfg["max_levels"], coarsest_max=cfg["coarsest_max"],
                                   tol=tol, **mo)
     sopts = pm.default_solver_opts(precision=precision, guess=guess, trsv_block=trsv_block, spatial_tol=stol,
-                                   autotune=autotune, coarse_tol=ctol)
+                                   autotune=autotune, coarse_tol=ctol, lds_mask=lds_mask)
     S = pm.Solver(probs, mopts, sopts, device=0)
     for i, d in enumerate(cfg["instances"]):
         S.set_source(i, d["src"], d["tkind"])
@@ -237,6 +238,26 @@ def test_autotune_same_result(torch, precision):
     say(f"  default {S0.group_info(0)['lds_mask']} tuned {gi['lds_mask']} ({gi['lds_bytes']} B)")
     (U1,), st1 = S1.solve_mgrit()
     assert gi["lds_mask"] & 1
+    assert torch.equal(U0, U1) and st0["vcycles"] == st1["vcycles"]
+
+
+@pytest.mark.parametrize("mask", [3 | 16, 1 | 16, 3])
+def test_forced_placement_same_result(torch, mask):
+    """Forced LDS placements, including the FP32 kernel build for two workgroups per CU (mask bit
+    16), compute the same arithmetic: bitwise the same trajectory and V-cycle count as the
+    default placement."""
+    name = "heat-p5-h64-Nt1024"
+    cfg = W.config(name)
+    cfg["instances"][0]["Nt"] = 64
+    cfg["instances"][0]["T"] = 1.0 / 16
+    say(f"case forced placement {mask} p=5 n=64 N_t=64")
+    S0 = make_solver(cfg, precision=1)
+    (U0,), st0 = S0.solve_mgrit()
+    S1 = make_solver(cfg, precision=1, lds_mask=mask)
+    gi = S1.group_info(0)
+    say(f"  default {S0.group_info(0)['lds_mask']} forced {gi['lds_mask']} ({gi['lds_bytes']} B)")
+    assert gi["lds_mask"] == mask
+    (U1,), st1 = S1.solve_mgrit()
     assert torch.equal(U0, U1) and st0["vcycles"] == st1["vcycles"]
 
 

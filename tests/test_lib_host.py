@@ -129,3 +129,19 @@ def test_invalid_arguments_rejected():
     with pytest.raises(pm.PmgritError) as e:
         S.set_source(0, [(-1, 1, 1.0)])
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("kw", [dict(lds_mask=-1), dict(lds_mask=32), dict(lds_mask=3, autotune=1),
+                                dict(lds_mask=3 | 16, precision=0), dict(lds_mask=7 | 16, precision=1),
+                                dict(lds_mask=2 | 16, precision=1)])
+def test_rejects_invalid_placement(kw):
+    """The forced LDS placement is checked at create: in range, not with the autotuner, and the
+    two-workgroups-per-CU build only in precision 1 with y (and at most d) in LDS."""
+    with pytest.raises(pm.PmgritError):
+        host_solver(3, 6, **kw)
+
+
+@pytest.mark.parametrize("kw", [dict(lds_mask=3 | 16, precision=1), dict(lds_mask=1 | 16, precision=1),
+                                dict(lds_mask=15), dict(lds_mask=1)])
+def test_accepts_valid_placement(kw):
+    host_solver(3, 6, **kw).close()
