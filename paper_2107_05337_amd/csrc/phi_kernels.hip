@@ -522,7 +522,26 @@ __device__ __forceinline__ void coarse_transform(int n1, const G<double>* __rest
       ia[u] = a0 + u < n1 ? a0 + u : n1 - 1;  // clamped: rows / columns past n1 are not stored
       ix[u] = x0 + u < n1 ? x0 + u : n1 - 1;
     }
-    for (int b = 0; b < n1; ++b) {
+    // two steps of b per trip: their V loads (global) are in flight together, so the loop
+    // pays the load latency once per two steps
+    int b = 0;
+    for (; b + 2 <= n1; b += 2) {
+      double w[2][4], v[2][4];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          w[s][u] = TRANS ? V[(b + s) * n1 + ia[u]] : V[ia[u] * n1 + b + s];
+          v[s][u] = in[(b + s) * n1 + ix[u]];
+        }
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[u][q] += w[s][u] * v[s][q];
+    }
+    for (; b < n1; ++b) {
       double w[4], v[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
