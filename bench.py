@@ -38,7 +38,8 @@ HBM_PEAK_GBS = 8000.0
 RHS_PER_BATCH = 128  # level-0 F-sweep width (N_t / m)
 
 
-def make(precision: int, guess: int = 2, autotune: int = 0, graph: int = 0, coarse_tol: float = 0.0):
+def make(precision: int, guess: int = 2, autotune: int = 0, graph: int = 0, coarse_tol: float = 0.0,
+         lds_mask: int = 0):
     import paper_2107_05337_amd as pm
     from paper_2107_05337_amd import workloads as W
 
@@ -46,7 +47,8 @@ def make(precision: int, guess: int = 2, autotune: int = 0, graph: int = 0, coar
     insts = [c["instances"][0] for c in cfgs]
     probs = [pm.problem(d["p"], d["n"], d["Nt"], d["kappa"], d["T"], d["domain"]) for d in insts]
     mo = pm.default_mgrit_opts(cfactor=8, max_levels=12, coarsest_max=8, tol=1e-10, use_graph=graph)
-    so = pm.default_solver_opts(precision=precision, guess=guess, autotune=autotune, coarse_tol=coarse_tol)
+    so = pm.default_solver_opts(precision=precision, guess=guess, autotune=autotune, coarse_tol=coarse_tol,
+                                lds_mask=lds_mask)
     S = pm.Solver(probs, mo, so, device=0)
     for i, d in enumerate(insts):
         S.set_source(i, d["src"], d["tkind"])
@@ -103,10 +105,10 @@ def unit_bytes(S, inst: int, precision: int) -> float:
 
 
 def run_variant(precision: int, steps: int, warmup: int, guess: int = 2, autotune: int = 0, graph: int = 0,
-                coarse_tol: float = 0.0, theta=None):
+                coarse_tol: float = 0.0, theta=None, lds_mask: int = 0):
     import torch
 
-    S, insts = make(precision, guess, autotune, graph, coarse_tol)
+    S, insts = make(precision, guess, autotune, graph, coarse_tol, lds_mask)
     if theta is not None:
         S.net_load(theta)
     outs = S.alloc_trajectories()

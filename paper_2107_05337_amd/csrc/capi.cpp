@@ -107,6 +107,7 @@ struct pmgrit_handle {
   struct Group {
     std::vector<int> inst;
     int mask = 0, lds_bytes = 0, nmax = 0, n1max = 0, ka = 2, rw = 8, maxrows = 1;
+    int ka8 = 2, rw8 = 16;  // the same for the 1024-thread build (8 lanes per row)
     float tuned_ms = 0.f;  // probe time of the chosen placement (autotune)
     LdsPlan plan{-1, -1, -1, -1, 512, 0, 0, 2};
     // placement of the sweeps with more workgroups than the device has CUs (the level-0 sweeps),
@@ -480,7 +481,7 @@ static pmgrit_status upload_vals(pmgrit_handle* H, const std::vector<double>& v,
     if (s_ != PMGRIT_OK) return s_; \
   } while (0)
 
-static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& T, int zidx, int RW) {
+static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& T, int zidx, int RW, int TG) {
   T.nlev = S.nlev;
   T.bs = S.bs;
   T.max_rows = S.max_rows;
@@ -525,7 +526,7 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
     // their natural order, zero-padded.  Dense rows: the columns from bq0 rounded down to 16
     // bytes (zeros in front) in natural order, zero-padded to a multiple of four 16-byte units;
     // bc = values per lane.  The kernel's lane g reads 16-byte units g, g + 4, ... of a row.
-    const int R = std::max(1, S.max_rows), AS = RW, TGh = 4;
+    const int R = std::max(1, S.max_rows), AS = RW, TGh = TG;
     const int V = H->fp32 ? 4 : 2;  // values per 16 bytes
     const size_t nslots = (size_t)(S.nlev + 2) * R + 1;
     std::vector<Meta4> meta(nslots, Meta4{-1, 0, 0, 0});
@@ -771,15 +772,17 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
         // of the group's instances over the 4 lanes per row, rounded up to a power of two
         const int maxo = inst_max_offblock(I);
         // ka in {2, 4, 8, 12, 16}: 16-byte units of 4 entries per lane beyond 2
-        const int need = (maxo + 3) / 4;
-        const int ka = need <= 2 ? 2 : std::min(16, (need + 3) / 4 * 4);
-        G.ka = std::max(G.ka, ka);
+        auto ka_for = [](int need) { return need <= 2 ? 2 : std::min(16, (need + 3) / 4 * 4); };
+        G.ka = std::max(G.ka, ka_for((maxo + 3) / 4));
+        G.ka8 = std::max(G.ka8, ka_for((maxo + 7) / 8));
       }
       G.rw = G.ka * 4;
+      G.rw8 = G.ka8 * 8;
       lds_plan(G.nmax, G.n1max, G.maxrows, vt, G.ka, dev_lds, G.mask, G.lds_bytes, G.plan);
       if (H->so.lds_mask) {  // placement chosen by the caller
         int bytes = 0;
-        const LdsPlan plan = lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, G.ka, dev_lds, H->so.lds_mask, bytes);
+        const LdsPlan plan = lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, (H->so.lds_mask & kT1024) ? G.ka8 : G.ka,
+                                           dev_lds, H->so.lds_mask, bytes);
         if (bytes == 0) return fail(PMGRIT_E_ARG, "lds_mask does not fit a launch group's LDS");
         G.mask = H->so.lds_mask;
         G.lds_bytes = bytes;
@@ -838,8 +841,10 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
       for (size_t t = 0; t < X1.a.size(); ++t) X1.a[t] = I.Mx.a[t] + Ld.c * I.Kx.a[t];
       TRY(upload_band(H, X1, -p, 2 * p + 1, Ld.X1));
       const int zidx = (G.mask & kY) ? G.plan.zidx : -1;  // prefetched path needs y in LDS
-      TRY(upload_tri(H, Lh.SL, Ld.L, zidx, G.rw));
-      TRY(upload_tri(H, Lh.SU, Ld.U, zidx, G.rw));
+      TRY(upload_tri(H, Lh.SL, Ld.L, zidx, G.rw, 4));
+      TRY(upload_tri(H, Lh.SU, Ld.U, zidx, G.rw, 4));
+      TRY(upload_tri(H, Lh.SL, Ld.L8, zidx, G.rw8, 8));
+      TRY(upload_tri(H, Lh.SU, Ld.U8, zidx, G.rw8, 8));
       TRY(upload_vec(H, Lh.tl, &d));
       Ld.tl = d;
       TRY(upload_vec(H, Lh.tdinv, &d));
@@ -1161,10 +1166,11 @@ static pmgrit_status autotune(pmgrit_handle* H) {
     // fastest placement for a probe of n right-hand sides
     auto probe = [&](int n, int& best_mask, int& best_bytes, LdsPlan& best_plan, float& best_ms) -> hipError_t {
       best_ms = 1e30f;
-      for (int mk : {15, 7, 3, 1, 3 | kOcc2, 1 | kOcc2}) {
+      for (int mk : {15, 7, 3, 1, 3 | kOcc2, 1 | kOcc2, 15 | kT1024, 7 | kT1024, 3 | kT1024, 1 | kT1024}) {
         if ((mk & kOcc2) && !H->fp32) continue;
         int bytes = 0;
-        const LdsPlan plan = lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, G.ka, dev_lds, mk, bytes);
+        const LdsPlan plan =
+            lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, (mk & kT1024) ? G.ka8 : G.ka, dev_lds, mk, bytes);
         if (bytes == 0 || ((mk & kOcc2) && 2 * bytes > dev_lds)) continue;
         hipError_t e = phi_prepare(H->fp32, mk, bytes);
         if (e != hipSuccess) return e;
@@ -1236,7 +1242,8 @@ pmgrit_status pmgrit_create(int32_t n_instances, const pmgrit_problem* probs, co
   if (so.nu1 < 1 || so.nu2 < 0 || !(so.ilut_droptol >= 0) || !(so.spatial_tol > 0) || so.max_vcycles < 1 ||
       (so.precision != 0 && so.precision != 1) || so.guess < 0 || so.guess > 3 || so.trsv_block < -1 ||
       so.autotune < 0 || so.autotune > 1 || !(so.coarse_tol >= 0) || so.coarse_tol >= 1 || so.lds_mask < 0 ||
-      so.lds_mask > 31 || (so.lds_mask && so.autotune) ||
+      so.lds_mask > 63 || (so.lds_mask && so.autotune) ||
+      ((so.lds_mask & kT1024) && ((so.lds_mask & kOcc2) || !(so.lds_mask & kY))) ||
       ((so.lds_mask & kOcc2) && (so.precision != 1 || (so.lds_mask & 15) != ((so.lds_mask & 15) & (kY | kD)) ||
                                  !(so.lds_mask & kY))))
     return fail(PMGRIT_E_ARG, "invalid solver options");

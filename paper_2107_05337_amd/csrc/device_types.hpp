@@ -59,7 +59,8 @@ struct BandDev {
 struct LevelDev {
   double dt, c;        // c = kappa dt_l
   BandDev X1;          // first-direction factor of A_l's first term: Mx + c Kx
-  TriDev L, U;         // ILUT(A_l) factors
+  TriDev L, U;         // ILUT(A_l) factors (slot tables for 4 lanes per row)
+  TriDev L8, U8;       // the same factors, slot tables for 8 lanes per row
   const double* tl;    // exact p = 1 solve: Thomas multipliers per mode [n1][n1]
   const double* tdinv; //                    inverse pivots per mode [n1][n1]
 };
@@ -123,5 +124,8 @@ enum : int { kY = 1, kD = 2, kS = 4, kX = 8 };
 // placement flag: the FP32 spatial-solve kernel built for two 512-thread workgroups per CU (at
 // most 128 VGPRs per lane); with an LDS plan of at most half the CU's LDS two chains then share a CU
 constexpr int kOcc2 = 16;
+// placement flag: the spatial-solve kernel built for 1024-thread workgroups (8 lanes per
+// triangular-solve row, slot tables in that layout); y must be in LDS
+constexpr int kT1024 = 32;
 
 }  // namespace pmg

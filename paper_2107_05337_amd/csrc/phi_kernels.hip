@@ -30,17 +30,13 @@ __device__ __forceinline__ const G<T>* gp(const T* p) {
   return (const G<T>*)p;
 }
 
-// Launch shape per V-cycle precision: 512 threads (4 lanes per row, 128 row slots per
-// triangular-solve level), so each thread has a 256-register budget for the prefetch buffers.
-template <typename VT>
-struct Cfg;
-template <>
-struct Cfg<double> {
-  static constexpr int NT = 512, TG = 4;
-};
-template <>
-struct Cfg<float> {
-  static constexpr int NT = 512, TG = 4;
+// Kernel builds: OCC 1 runs 512 threads (4 lanes per triangular-solve row, 128 row slots per
+// level, a 256-register budget per thread), OCC 2 the same limited to 128 registers (two
+// workgroups per CU), OCC 3 1024 threads (8 lanes per row, 128 registers): shorter per-lane
+// work in every phase of one solve.
+template <int OCC>
+struct Build {
+  static constexpr int NT = OCC == 3 ? 1024 : 512, TG = NT / kRowSlots;
 };
 
 template <int G, typename T>
@@ -147,12 +143,17 @@ __device__ __forceinline__ double pass_y(int ncols, int nin, const BandDev& Bd, 
     const G<AT>* b = B + o * w;
     AT s = 0;
     if (w <= kBandMax) {
+      // the row's coefficients first, all in flight together (kept ahead of their use even
+      // where registers are scarce)
+      AT bb[kBandMax];
+#pragma unroll
+      for (int d = 0; d < kBandMax; ++d) bb[d] = b[d < w ? d : w - 1];
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int d = 0; d < kBandMax; ++d) {
         int j = o + lo + d;
         j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
-        const AT bd = b[d < w ? d : w - 1];
-        s += (d < w ? bd : (AT)0) * (AT)T[j * ncols + c];
+        s += (d < w ? bb[d] : (AT)0) * (AT)T[j * ncols + c];
       }
     } else {
       for (int d = 0; d < w; ++d) {
@@ -217,6 +218,14 @@ __device__ __forceinline__ T quad_sum(T v) {
   v += dpp_mov<0x4E>(v);  // quad_perm [2, 3, 0, 1]
   return v;
 }
+// sum over the TG (4 or 8) lanes of a row; for 8, the quads' sums meet through row_half_mirror
+// (lane i of each 8-lane group reads lane 7 - i)
+template <int TG, typename T>
+__device__ __forceinline__ T row_sum(T v) {
+  v = quad_sum(v);
+  if constexpr (TG == 8) v += dpp_mov<0x141>(v);
+  return v;
+}
 
 // buffer descriptor over a table of the prefetched solve (raw, stride 0, kBufBytes long):
 // a load at an offset of kBufBytes or more returns zeros without touching memory
@@ -263,13 +272,15 @@ __device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t rs, int off, uns
 template <typename VT, bool IN_GLOBAL, int KA, int OCC>
 __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, const VT* in_g, L3<VT>* y,
                                        L3<VT>* sbuf) {
-  constexpr int TG = Cfg<VT>::TG, RW = KA * TG, V = 16 / (int)sizeof(VT), BCM = 20;
+  constexpr int TG = Build<OCC>::TG, RW = KA * TG, V = 16 / (int)sizeof(VT);
+  // dense values per lane: a row holds up to kDenseMax values after up to V - 1 of alignment
+  constexpr int BCM = (kDenseMax + V - 1 + TG * V - 1) / (TG * V) * V;
   constexpr int WA = KA < V ? KA : V;  // off-block entries per unit
   constexpr int NU = KA / WA;          // off-block units per lane
   constexpr int ND = BCM / V;          // dense units per lane
   constexpr int VB = (int)sizeof(VT);
   typedef VT VV __attribute__((ext_vector_type(V)));
-  static_assert(TG == 4, "quad sums assume 4 lanes per row");
+  static_assert(TG == 4 || TG == 8, "row sums over 4 or 8 lanes");
   Tp = uniform_ptr(Tp);  // the schedule header is the same for the whole workgroup
   const __amdgpu_buffer_rsrc_t rval = table_rsrc(Tp->aval), rcol = table_rsrc(Tp->acol),
                                rden = table_rsrc(Tp->dfast), rmeta = table_rsrc(Tp->meta),
@@ -286,10 +297,11 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
     }
     return;
   }
-  // slot metadata: loaded by lane 0 of the quad, broadcast to the quad when its level comes
+  // slot metadata: loaded by lane 0 of each quad of the row, broadcast to the quad when its
+  // level comes
   auto load_meta = [&](int l, Meta4& m) {
     unsigned u[4];
-    buf_load<16>(rmeta, g == 0 ? (slot ? 1 + l * R + r : 0) * 16 : kOff, u);
+    buf_load<16>(rmeta, (g & 3) == 0 ? (slot ? 1 + l * R + r : 0) * 16 : kOff, u);
     m = Meta4{(int)u[0], (int)u[1], (int)u[2], (int)u[3]};
   };
   auto bcast = [&](Meta4& m) {
@@ -304,7 +316,7 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
     const int base = RW + (l * R + r) * RW;
 #pragma unroll
     for (int k = 0; k < NU; ++k) {
-      const int e0 = (k * 4 + g) * WA;
+      const int e0 = (k * TG + g) * WA;
       const bool live = e0 < m.na;
       unsigned uv[WA * VB / 4], uc[WA];
       buf_load<WA * VB>(rval, live ? (base + e0) * VB : kOff, uv);
@@ -338,7 +350,7 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
 #pragma unroll
     for (int k = 0; k < ND; ++k) {
       unsigned u[4];
-      buf_load<16>(rden, k * V < bc ? (m.bo + (k * 4 + g) * V) * VB : kOff, u);
+      buf_load<16>(rden, k * V < bc ? (m.bo + (k * TG + g) * V) * VB : kOff, u);
 #pragma unroll
       for (int e = 0; e < V; ++e) {
         if constexpr (VB == 8)
@@ -352,7 +364,7 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
     VT s = 0;
 #pragma unroll
     for (int j = 0; j < KA; ++j) s += av[j] * yz[ac[j]];
-    s = quad_sum(s);
+    s = row_sum<TG>(s);
     if (g == 0 && row >= 0) sbuf[r] = xin - s;
   };
   // sbuf beyond the level's rows holds finite values, met by zero coefficients
@@ -361,11 +373,11 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
     const L3<VV>* sp = (const L3<VV>*)(sbuf + (m.bqc & 0xffff));
 #pragma unroll
     for (int k = 0; k < ND; ++k) {
-      const VV sv = sp[k * 4 + g];
+      const VV sv = sp[k * TG + g];
 #pragma unroll
       for (int e = 0; e < V; ++e) s += bv[k * V + e] * sv[e];
     }
-    s = quad_sum(s);
+    s = row_sum<TG>(s);
     if (g == 0 && m.row >= 0) y[m.row] = s;
   };
   if constexpr (sizeof(VT) == 4) {
@@ -445,9 +457,9 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
 }
 
 // General path (any schedule, y in LDS or global): same two phases with loops, full barriers.
-template <typename VT>
+template <typename VT, int NT>
 __device__ void trsv_general(const TriDev& T, const VT* in, VT* y, VT* sbuf) {
-  constexpr int NT = Cfg<VT>::NT, GA = 8, GB = 8;
+  constexpr int GA = 8, GB = 8;
   const G<VT>* __restrict__ ov = gp((const VT*)T.ov);
   const G<VT>* __restrict__ dv = gp((const VT*)T.dval);
   const G<int>* __restrict__ lev_ptr = gp(T.lev_ptr);
@@ -497,7 +509,7 @@ __device__ __forceinline__ void trsv(const TriDev& T, int ka, int zidx, const VT
     else
       trsv_fast<VT, IN_GLOBAL, 16, OCC>(&T, zidx, in, yl, sl);
   } else {
-    trsv_general<VT>(T, in, y, sbuf);
+    trsv_general<VT, Build<OCC>::NT>(T, in, y, sbuf);
   }
   __syncthreads();
 }
@@ -507,56 +519,57 @@ __device__ __forceinline__ void trsv(const TriDev& T, int ka, int zidx, const VT
 // system per mode of the second direction (Thomas, precomputed LDL^T).  c1 in / out, c2 temp.
 // ---------------------------------------------------------------------------------------
 // dense transform over the second direction, out[a][ix] = sum_b W(a, b) in[b][ix] for a, ix < n1,
-// with W(a, b) = V[b][a] (transposed) or V[a][b]: 4 x 4 output tiles per thread, so each loaded
-// V entry and input entry serves four products
+// with W(a, b) = V[b][a] (transposed) or V[a][b]: T x T output tiles per thread (T = 4 with 512
+// threads, 2 with 1024: about one tile per thread at the sizes here, and few registers), so
+// each loaded V entry and input entry serves T products; two steps of b per trip keep the V
+// loads (global) of both in flight together
 template <int NT, bool TRANS>
 __device__ __forceinline__ void coarse_transform(int n1, const G<double>* __restrict__ V, const double* in,
                                                  double* out) {
-  const int nt = (n1 + 3) / 4, tiles = nt * nt;
+  constexpr int T = NT >= 1024 ? 2 : 4;
+  const int nt = (n1 + T - 1) / T, tiles = nt * nt;
   for (int t = threadIdx.x; t < tiles; t += NT) {
-    const int a0 = (t / nt) * 4, x0 = (t % nt) * 4;
-    double acc[4][4] = {};
-    int ia[4], ix[4];
+    const int a0 = (t / nt) * T, x0 = (t % nt) * T;
+    double acc[T][T] = {};
+    int ia[T], ix[T];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < T; ++u) {
       ia[u] = a0 + u < n1 ? a0 + u : n1 - 1;  // clamped: rows / columns past n1 are not stored
       ix[u] = x0 + u < n1 ? x0 + u : n1 - 1;
     }
-    // two steps of b per trip: their V loads (global) are in flight together, so the loop
-    // pays the load latency once per two steps
     int b = 0;
     for (; b + 2 <= n1; b += 2) {
-      double w[2][4], v[2][4];
+      double w[2][T], v[2][T];
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < T; ++u) {
           w[s][u] = TRANS ? V[(b + s) * n1 + ia[u]] : V[ia[u] * n1 + b + s];
           v[s][u] = in[(b + s) * n1 + ix[u]];
         }
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < T; ++u)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[u][q] += w[s][u] * v[s][q];
+          for (int q = 0; q < T; ++q) acc[u][q] += w[s][u] * v[s][q];
     }
     for (; b < n1; ++b) {
-      double w[4], v[4];
+      double w[T], v[T];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < T; ++u) {
         w[u] = TRANS ? V[b * n1 + ia[u]] : V[ia[u] * n1 + b];
         v[u] = in[b * n1 + ix[u]];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < T; ++u)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[u][q] += w[u] * v[q];
+        for (int q = 0; q < T; ++q) acc[u][q] += w[u] * v[q];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < T; ++u)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < T; ++q)
         if (a0 + u < n1 && x0 + q < n1) out[(a0 + u) * n1 + x0 + q] = acc[u][q];
   }
 }
@@ -623,17 +636,20 @@ template <typename VT, int MASK, int OCC>
 __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, const VT* r, VT* d, VT* y, VT* s,
                        VT* sbuf, int ka, int zidx) {
   constexpr bool YL = MASK & kY;
-  constexpr int NT = Cfg<VT>::NT;
+  constexpr int NT = Build<OCC>::NT;
   const int n = I.ndof;
+  // the 1024-thread build reads the factors' slot tables laid out for 8 lanes per row
+  const TriDev& TL = OCC == 3 ? L.L8 : L.L;
+  const TriDev& TU = OCC == 3 ? L.U8 : L.U;
   // step 1: pre-smoothing d = S r, then nu1 - 1 further steps d += S (r - A d)
-  trsv<VT, YL, true, OCC>(L.L, ka, zidx, r, y, sbuf);
-  trsv<VT, YL, !YL, OCC>(L.U, ka, zidx, y, y, sbuf);
+  trsv<VT, YL, true, OCC>(TL, ka, zidx, r, y, sbuf);
+  trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf);
   for (int i = threadIdx.x; i < n; i += NT) d[i] = y[i];
   __syncthreads();
   for (int m = 1; m < nu1; ++m) {
     apply_A<NT, VT, OCC>(I, L, d, r, s, y);
-    trsv<VT, YL, !(MASK & kS), OCC>(L.L, ka, zidx, s, y, sbuf);
-    trsv<VT, YL, !YL, OCC>(L.U, ka, zidx, y, y, sbuf);
+    trsv<VT, YL, !(MASK & kS), OCC>(TL, ka, zidx, s, y, sbuf);
+    trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf);
     for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
     __syncthreads();
   }
@@ -655,8 +671,8 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
   // step 5: nu2 post-smoothing steps d += S (r - A d)
   for (int m = 0; m < nu2; ++m) {
     apply_A<NT, VT, OCC>(I, L, d, r, s, y);
-    trsv<VT, YL, !(MASK & kS), OCC>(L.L, ka, zidx, s, y, sbuf);
-    trsv<VT, YL, !YL, OCC>(L.U, ka, zidx, y, y, sbuf);
+    trsv<VT, YL, !(MASK & kS), OCC>(TL, ka, zidx, s, y, sbuf);
+    trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf);
     for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
     __syncthreads();
   }
@@ -664,7 +680,7 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
 
 template <typename VT, int MASK, int OCC>
 __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan) {
-  constexpr int NT = Cfg<VT>::NT;
+  constexpr int NT = Build<OCC>::NT;
   extern __shared__ __align__(16) unsigned char smem[];
   const PhiJob job = P.jobs[blockIdx.x];
   const InstDev& I = P.inst[job.inst];
@@ -837,19 +853,32 @@ __global__ void norm_reduce_kernel(const double* __restrict__ nrm2, const int* _
 // one workgroup per job; phi_kernel_o2 is the same code limited to 128 VGPRs per lane, so that
 // two workgroups fit a CU when the LDS plan leaves room for them
 template <typename VT, int MASK>
-__global__ void __launch_bounds__(Cfg<VT>::NT) phi_kernel(PhiParams P, LdsPlan plan) {
+__global__ void __launch_bounds__(512) phi_kernel(PhiParams P, LdsPlan plan) {
   phi_body<VT, MASK, 1>(P, plan);
 }
 template <typename VT, int MASK>
-__global__ void __launch_bounds__(Cfg<VT>::NT) __attribute__((amdgpu_waves_per_eu(4))) phi_kernel_o2(PhiParams P,
-                                                                                                 LdsPlan plan) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) phi_kernel_o2(PhiParams P,
+                                                                                          LdsPlan plan) {
   phi_body<VT, MASK, 2>(P, plan);
+}
+// the 1024-thread build (placement flag kT1024)
+template <typename VT, int MASK>
+__global__ void __launch_bounds__(1024) phi_kernel_t(PhiParams P, LdsPlan plan) {
+  phi_body<VT, MASK, 3>(P, plan);
 }
 
 using PhiFn = void (*)(PhiParams, LdsPlan);
 
 template <typename VT>
 static PhiFn pick(int mask) {
+  if (mask & kT1024) {
+    switch (mask & 15) {
+      case 15: return phi_kernel_t<VT, 15>;
+      case 7: return phi_kernel_t<VT, 7>;
+      case 3: return phi_kernel_t<VT, 3>;
+      default: return phi_kernel_t<VT, 1>;
+    }
+  }
   if constexpr (sizeof(VT) == 4) {
     if (mask == (3 | kOcc2)) return phi_kernel_o2<VT, 3>;
     if (mask == (1 | kOcc2)) return phi_kernel_o2<VT, 1>;
@@ -879,7 +908,7 @@ hipError_t phi_prepare(int fp32, int mask, int lds_bytes) {
 hipError_t phi_launch(int fp32, int mask, int lds_bytes, const PhiParams& P, const LdsPlan& plan, int nblocks,
                       hipStream_t st) {
   PhiFn f = fp32 ? pick<float>(mask) : pick<double>(mask);
-  hipLaunchKernelGGL(f, dim3(nblocks), dim3(fp32 ? Cfg<float>::NT : Cfg<double>::NT), lds_bytes, st, P, plan);
+  hipLaunchKernelGGL(f, dim3(nblocks), dim3(mask & kT1024 ? 1024 : 512), lds_bytes, st, P, plan);
   return hipGetLastError();
 }
 
