@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <atomic>
 #include <memory>
@@ -109,11 +110,12 @@ struct pmgrit_handle {
     int mask = 0, lds_bytes = 0, nmax = 0, n1max = 0, ka = 2, rw = 8, maxrows = 1;
     int ka8 = 2, rw8 = 16;  // the same for the 1024-thread build (8 lanes per row)
     float tuned_ms = 0.f;  // probe time of the chosen placement (autotune)
-    LdsPlan plan{-1, -1, -1, -1, 512, 0, 0, 2};
+    LdsPlan plan{-1, -1, -1, -1, 512, 0, 0, 2, -1, 0};
+    int winw = 0;  // LDS window words of the triangular solves when y is not in LDS (0: none)
     // placement of the sweeps with more workgroups than the device has CUs (the level-0 sweeps),
     // where two workgroups per CU can pay; mask / lds_bytes / plan serve the narrower ones
     int wmask = 0, wbytes = 0;
-    LdsPlan wplan{-1, -1, -1, -1, 512, 0, 0, 2};
+    LdsPlan wplan{-1, -1, -1, -1, 512, 0, 0, 2, -1, 0};
     std::vector<JobList> jF, jC, jRES;  // per level: F-relaxation chains, C-steps, C-point residuals
     JobList jCoarsest, jSeq;
     // single-step lists of the learned warm start: level-0 F steps per position s in the
@@ -345,8 +347,9 @@ static pmgrit_status setup_level(const pmgrit_handle* H, InstHost& I, int l, std
     const int parts = (I.Nin + kDenseMax - 1) / kDenseMax;
     bs = (I.Nin + parts - 1) / parts;
   }
-  Lv.SL = build_schedule(Lv.L, false, bs);
-  Lv.SU = build_schedule(Lv.U, true, bs);
+  // at most kRowSlots rows per level, the prefetched path's row slots
+  Lv.SL = build_schedule(Lv.L, false, bs, kRowSlots);
+  Lv.SU = build_schedule(Lv.U, true, bs, kRowSlots);
   // Thomas data per mode k: T_k = G + c lam_k H with G = M1x + c K1x
   const int n1 = I.n1;
   Lv.tl.assign((size_t)n1 * n1, 0.0);
@@ -481,7 +484,42 @@ static pmgrit_status upload_vals(pmgrit_handle* H, const std::vector<double>& v,
     if (s_ != PMGRIT_OK) return s_; \
   } while (0)
 
-static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& T, int zidx, int RW, int TG) {
+// winW > 0: window mode, off-block columns become slots of an LDS window of winW grid lines of winN
+// rows (line j at slot j mod winW).  Valid when the grid lines each level writes advance
+// monotonically (up for L, down for U) and each level's rows and off-block columns span at most
+// winW lines: a level then overwrites only the slots of lines no later level reads (a block may
+// straddle two lines when a line is split into blocks)
+static bool window_fits(const TriSchedule& S, int winW, int winN) {
+  int pa = -1, pb = -1, dir = 0;
+  for (int l = 0; l < S.nlev; ++l) {
+    int a = INT32_MAX, b = -1, lo = INT32_MAX, hi = -1;
+    for (int q = S.lev_ptr[l]; q < S.lev_ptr[l + 1]; ++q) {
+      const int line = S.row[q] / winN;
+      a = std::min(a, line);
+      b = std::max(b, line);
+      for (int k = S.orp[q]; k < S.orp[q + 1]; ++k) {
+        lo = std::min(lo, S.oci[k] / winN);
+        hi = std::max(hi, S.oci[k] / winN);
+      }
+    }
+    if (b < 0) continue;
+    if (std::max(b, hi) - std::min(a, lo) > winW - 1) return false;
+    if (pb >= 0) {
+      const int d = (a > pa || b > pb) ? 1 : (a < pa || b < pb) ? -1 : 0;
+      if (d != 0) {
+        if ((d > 0 && (a < pa || b < pb)) || (d < 0 && (a > pa || b > pb))) return false;
+        if (dir != 0 && d != dir) return false;
+        dir = d;
+      }
+    }
+    pa = a;
+    pb = b;
+  }
+  return true;
+}
+
+static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& T, int zidx, int RW, int TG, int winW,
+                                int winN) {
   T.nlev = S.nlev;
   T.bs = S.bs;
   T.max_rows = S.max_rows;
@@ -494,9 +532,13 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
   for (int c : S.dq0) maxq = std::max(maxq, c);
   const size_t aslots = ((size_t)S.nlev * std::max(1, S.max_rows) + 1) * (size_t)RW;
   T.fast = (zidx >= 0 && S.max_rows <= kRowSlots && maxo <= RW && maxo <= kOffMax && maxd <= kDenseMax &&
-            maxq < 65536 && S.dval.size() + 1 < (size_t)INT32_MAX && aslots * sizeof(double) < (size_t)kBufBytes)
+            maxq < 65536 && S.dval.size() + 1 < (size_t)INT32_MAX && aslots * sizeof(double) < (size_t)kBufBytes &&
+            (winW == 0 || window_fits(S, winW, winN)))
                ? 1
                : 0;
+  T.winW = T.fast ? winW : 0;
+  T.winN = winN;
+  auto colmap = [&](int c) { return T.winW ? (c / winN % winW) * winN + c % winN : c; };
   int* p;
   TRY(upload_vec(H, S.lev_ptr, &p));
   T.lev_ptr = p;
@@ -549,7 +591,7 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
         meta[1 + sl] = Meta4{S.row[q], (int)bo, q0 | (bc << 16), na};
         for (int t = 0; t < na; ++t) {
           aval[(1 + sl) * AS + t] = S.ov[S.orp[q] + t];
-          acol[(1 + sl) * AS + t] = S.oci[S.orp[q] + t] - zidx;
+          acol[(1 + sl) * AS + t] = colmap(S.oci[S.orp[q] + t]) - zidx;
         }
       }
     T.R = R;
@@ -615,7 +657,18 @@ static pmgrit_status upload_band(pmgrit_handle* H, const Dense& full, int lo, in
 // LDS plan for a launch configuration: the largest set of work vectors that fits, in the order
 // y, d, s, x.  y is an FP64-sized slot plus a zero word (it also holds the FP64 Kronecker
 // temporaries and a p = 1 vector), s holds a V-cycle vector or an FP64 p = 1 vector.
-static void lds_plan(int nmax, int n1max, int maxrows, int vt, int ka, int dev_lds, int& mask, int& bytes,
+// A placement without y in LDS gets the triangular solves' LDS window (winw words, 0: none)
+// when it fits.
+static void add_window(LdsPlan& plan, int& off, int mask, int vt, int winw, int dev_lds) {
+  if ((mask & kY) || winw <= 0) return;
+  const int sz = (winw * vt + 15) / 16 * 16;
+  if (off + sz > dev_lds) return;
+  plan.off_win = off;
+  plan.zwin = winw - 1;
+  off += sz;
+}
+
+static void lds_plan(int nmax, int n1max, int maxrows, int vt, int ka, int dev_lds, int winw, int& mask, int& bytes,
                      LdsPlan& out) {
   auto al = [](int b) { return (b + 15) / 16 * 16; };
   const int base = 512 + al(std::max(maxrows, 256) * vt);  // block-sum scratch, sbuf (256 words)
@@ -625,11 +678,12 @@ static void lds_plan(int nmax, int n1max, int maxrows, int vt, int ka, int dev_l
   for (int mi = 0; mi < 5; ++mi) {
     const int mk = masks[mi];
     int off = base;
-    LdsPlan plan{-1, -1, -1, -1, 512, nmax, nmax * 8 / vt, ka};
+    LdsPlan plan{-1, -1, -1, -1, 512, nmax, nmax * 8 / vt, ka, -1, 0};
     if (mk & kY) { plan.off_y = off; off += sz_y; }
     if (mk & kD) { plan.off_d = off; off += sz_d; }
     if (mk & kS) { plan.off_s = off; off += sz_s; }
     if (mk & kX) { plan.off_x = off; off += sz_x; }
+    add_window(plan, off, mk, vt, winw, dev_lds);
     if (off <= dev_lds || mk == 0) {
       mask = mk;
       bytes = off;
@@ -640,14 +694,16 @@ static void lds_plan(int nmax, int n1max, int maxrows, int vt, int ka, int dev_l
 }
 
 // LDS plan with exactly the vectors of `mask` in LDS (bytes = 0 when it does not fit)
-static LdsPlan lds_plan_mask(int nmax, int n1max, int maxrows, int vt, int ka, int dev_lds, int mask, int& bytes) {
+static LdsPlan lds_plan_mask(int nmax, int n1max, int maxrows, int vt, int ka, int dev_lds, int winw, int mask,
+                             int& bytes) {
   auto al = [](int b) { return (b + 15) / 16 * 16; };
   int off = 512 + al(std::max(maxrows, 256) * vt);
-  LdsPlan plan{-1, -1, -1, -1, 512, nmax, nmax * 8 / vt, ka};
+  LdsPlan plan{-1, -1, -1, -1, 512, nmax, nmax * 8 / vt, ka, -1, 0};
   if (mask & kY) { plan.off_y = off; off += al(nmax * 8 + 16); }
   if (mask & kD) { plan.off_d = off; off += al(nmax * vt); }
   if (mask & kS) { plan.off_s = off; off += al(std::max(nmax * vt, n1max * 8)); }
   if (mask & kX) { plan.off_x = off; off += al(nmax * 8); }
+  add_window(plan, off, mask, vt, winw, dev_lds);
   bytes = off <= dev_lds ? off : 0;
   return plan;
 }
@@ -752,7 +808,7 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
       const InstHost& I = H->inst[i];
       int bytes;
       LdsPlan pl;
-      lds_plan(I.ndof, I.ndof1, inst_maxrows(I), vt, 16, dev_lds, mk[i], bytes, pl);
+      lds_plan(I.ndof, I.ndof1, inst_maxrows(I), vt, 16, dev_lds, (I.p + 3) * I.Nin + 1, mk[i], bytes, pl);
     }
     for (int want : {15, 7, 3, 1, 0}) {
       pmgrit_handle::Group G;
@@ -775,14 +831,16 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
         auto ka_for = [](int need) { return need <= 2 ? 2 : std::min(16, (need + 3) / 4 * 4); };
         G.ka = std::max(G.ka, ka_for((maxo + 3) / 4));
         G.ka8 = std::max(G.ka8, ka_for((maxo + 7) / 8));
+        // LDS window of the triangular solves when y is not in LDS: p + 3 grid lines and a zero word
+        G.winw = std::max(G.winw, (I.p + 3) * I.Nin + 1);
       }
       G.rw = G.ka * 4;
       G.rw8 = G.ka8 * 8;
-      lds_plan(G.nmax, G.n1max, G.maxrows, vt, G.ka, dev_lds, G.mask, G.lds_bytes, G.plan);
+      lds_plan(G.nmax, G.n1max, G.maxrows, vt, G.ka, dev_lds, G.winw, G.mask, G.lds_bytes, G.plan);
       if (H->so.lds_mask) {  // placement chosen by the caller
         int bytes = 0;
         const LdsPlan plan = lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, (H->so.lds_mask & kT1024) ? G.ka8 : G.ka,
-                                           dev_lds, H->so.lds_mask, bytes);
+                                           dev_lds, G.winw, H->so.lds_mask, bytes);
         if (bytes == 0) return fail(PMGRIT_E_ARG, "lds_mask does not fit a launch group's LDS");
         G.mask = H->so.lds_mask;
         G.lds_bytes = bytes;
@@ -840,11 +898,15 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
       Dense X1 = I.Mx;
       for (size_t t = 0; t < X1.a.size(); ++t) X1.a[t] = I.Mx.a[t] + Ld.c * I.Kx.a[t];
       TRY(upload_band(H, X1, -p, 2 * p + 1, Ld.X1));
-      const int zidx = (G.mask & kY) ? G.plan.zidx : -1;  // prefetched path needs y in LDS
-      TRY(upload_tri(H, Lh.SL, Ld.L, zidx, G.rw, 4));
-      TRY(upload_tri(H, Lh.SU, Ld.U, zidx, G.rw, 4));
-      TRY(upload_tri(H, Lh.SL, Ld.L8, zidx, G.rw8, 8));
-      TRY(upload_tri(H, Lh.SU, Ld.U8, zidx, G.rw8, 8));
+      // the prefetched path reads y from LDS: the y slot, or the window of the last p + 3 grid
+      // lines when y is in global memory (the 1024-thread build needs the y slot)
+      const bool yl = G.mask & kY, win = !yl && G.plan.off_win >= 0;
+      const int zidx = yl ? G.plan.zidx : win ? G.plan.zwin : -1;
+      const int wl = win ? I.p + 3 : 0;
+      TRY(upload_tri(H, Lh.SL, Ld.L, zidx, G.rw, 4, wl, I.Nin));
+      TRY(upload_tri(H, Lh.SU, Ld.U, zidx, G.rw, 4, wl, I.Nin));
+      TRY(upload_tri(H, Lh.SL, Ld.L8, yl ? zidx : -1, G.rw8, 8, 0, I.Nin));
+      TRY(upload_tri(H, Lh.SU, Ld.U8, yl ? zidx : -1, G.rw8, 8, 0, I.Nin));
       TRY(upload_vec(H, Lh.tl, &d));
       Ld.tl = d;
       TRY(upload_vec(H, Lh.tdinv, &d));
@@ -1170,7 +1232,7 @@ static pmgrit_status autotune(pmgrit_handle* H) {
         if ((mk & kOcc2) && !H->fp32) continue;
         int bytes = 0;
         const LdsPlan plan =
-            lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, (mk & kT1024) ? G.ka8 : G.ka, dev_lds, mk, bytes);
+            lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, (mk & kT1024) ? G.ka8 : G.ka, dev_lds, G.winw, mk, bytes);
         if (bytes == 0 || ((mk & kOcc2) && 2 * bytes > dev_lds)) continue;
         hipError_t e = phi_prepare(H->fp32, mk, bytes);
         if (e != hipSuccess) return e;
@@ -1182,14 +1244,17 @@ static pmgrit_status autotune(pmgrit_handle* H) {
         P.bgiven = b;
         P.xgiven = x;
         P.guess = 0;
-        float ms = 0.f;
-        for (int rep = 0; rep < 2; ++rep) {
+        // the best of three launches after a warm-up one (first-touch and cache effects)
+        float ms = 1e30f;
+        for (int rep = 0; rep < 4; ++rep) {
+          float t = 0.f;
           if ((e = hipMemset(x, 0, sizeof(double) * hb.size())) != hipSuccess) return e;
           if ((e = hipEventRecord(e0, nullptr)) != hipSuccess) return e;
           if ((e = phi_launch(H->fp32, mk, bytes, P, plan, n, nullptr)) != hipSuccess) return e;
           if ((e = hipEventRecord(e1, nullptr)) != hipSuccess) return e;
           if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
-          if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return e;
+          if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return e;
+          if (rep > 0) ms = std::min(ms, t);
         }
         if (ms < best_ms) {
           best_ms = ms;

@@ -29,7 +29,11 @@ struct Meta4 {
 struct TriDev {
   int nlev, bs, max_rows, fast;  // fast: the schedule fits the prefetched register path
   // prefetched path: slot tables with addresses computable from (level, row slot, lane)
-  int R, AS, pad0, pad1;         // row slots per level, off-block row width (ka * lanes per row)
+  int R, AS;                     // row slots per level, off-block row width (ka * lanes per row)
+  // window mode (winW > 0, y not in LDS): the off-block columns are slots of an LDS window of the
+  // last winW grid lines of winN rows each, line j at slot (j mod winW), so each level reads the
+  // lines it couples to from LDS while the solution goes to y in global memory
+  int winW, winN;
   // entry 0 of every table is a reserved zero / empty slot
   const Meta4* meta;             // [1 + (nlev + 2) * R]
   const void* dfast;             // dense rows, natural column order, 4 * Meta4::bc values each
@@ -118,6 +122,8 @@ struct LdsPlan {
   int off_y, off_d, off_s, off_x, off_sbuf, nmax;
   int zidx;       // index (in V-cycle words) of the always-zero word at the end of the y slot
   int ka;         // off-block entries per lane of the prefetched triangular solves (2, 4, 8, 16)
+  int off_win;    // y not in LDS: LDS window of the triangular solves (-1: none)
+  int zwin;       // index (in V-cycle words) of the window's always-zero word
 };
 
 enum : int { kY = 1, kD = 2, kS = 4, kX = 8 };

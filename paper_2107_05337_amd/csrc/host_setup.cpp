@@ -322,7 +322,7 @@ bool ilut(const Csr& A, double tau, const std::vector<int>& lcap, const std::vec
 // ---------------------------------------------------------------------------------------
 // blocked level schedule
 // ---------------------------------------------------------------------------------------
-TriSchedule build_schedule(const Csr& T, bool upper, int bs) {
+TriSchedule build_schedule(const Csr& T, bool upper, int bs, int cap) {
   TriSchedule S;
   const int n = T.nr;
   S.n = n;
@@ -343,10 +343,22 @@ TriSchedule build_schedule(const Csr& T, bool upper, int bs) {
       }
     return l;
   };
+  // blocks in dependency order, each at the first level after its dependencies that still has
+  // room for its rows (cap rows per level, 0: no cap); a block's arithmetic does not depend on
+  // its level, only the number of levels does
+  std::vector<int> used;
+  auto place = [&](int b) {
+    const int m = std::min(n, b * bs + bs) - b * bs;
+    int l = dep_level(b);
+    while (cap > 0 && l < (int)used.size() && used[l] + m > cap) ++l;
+    if (l >= (int)used.size()) used.resize(l + 1, 0);
+    used[l] += m;
+    lev[b] = l;
+  };
   if (!upper)
-    for (int b = 0; b < nb; ++b) lev[b] = dep_level(b);
+    for (int b = 0; b < nb; ++b) place(b);
   else
-    for (int b = nb - 1; b >= 0; --b) lev[b] = dep_level(b);
+    for (int b = nb - 1; b >= 0; --b) place(b);
   int nlev = 0;
   for (int b = 0; b < nb; ++b) nlev = std::max(nlev, lev[b] + 1);
   S.nlev = nlev;

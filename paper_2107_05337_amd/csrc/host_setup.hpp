@@ -83,7 +83,7 @@ struct TriSchedule {
   std::vector<int64_t> doff;       //              values dval[doff[q] ..]
   std::vector<double> dval;
 };
-TriSchedule build_schedule(const Csr& T, bool upper, int bs);
+TriSchedule build_schedule(const Csr& T, bool upper, int bs, int cap);
 
 // Exact p = 1 solve by fast diagonalisation: (G kron ...) see host_setup.cpp.
 struct CoarseFdm {

@@ -269,9 +269,11 @@ __device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t rs, int off, uns
 // table (zeros, no memory traffic), so the loop has no divergent branches and a fixed number of
 // loads in flight, and each wait covers only the data about to be used.  Off-block columns are
 // stored relative to the zero word zidx, so a zeroed unit is a zero coefficient on that word.
-template <typename VT, bool IN_GLOBAL, int KA, int OCC>
+// With WIN, y is the LDS window of the last winW grid lines (columns in the tables are window
+// slots) and each solved row also goes to yg, the solution in global memory.
+template <typename VT, bool IN_GLOBAL, int KA, int OCC, bool WIN>
 __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, const VT* in_g, L3<VT>* y,
-                                       L3<VT>* sbuf) {
+                                       L3<VT>* sbuf, VT* yg) {
   constexpr int TG = Build<OCC>::TG, RW = KA * TG, V = 16 / (int)sizeof(VT);
   // dense values per lane: a row holds up to kDenseMax values after up to V - 1 of alignment
   constexpr int BCM = (kDenseMax + V - 1 + TG * V - 1) / (TG * V) * V;
@@ -289,6 +291,8 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
   const int r = threadIdx.x / TG, g = threadIdx.x & (TG - 1);
   const bool slot = r < R;
   const L3<VT>* yz = y + __builtin_amdgcn_readfirstlane(zidx);
+  const int winW = WIN ? __builtin_amdgcn_readfirstlane(Tp->winW) : 0;
+  const int winN = WIN ? __builtin_amdgcn_readfirstlane(Tp->winN) : 1;
   if ((int)((threadIdx.x & ~63) / TG) >= R) {
     // a wavefront whose row slots are all empty only keeps the barriers of the level loop
     for (int l = 0; l < nlev; ++l) {
@@ -378,7 +382,15 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
       for (int e = 0; e < V; ++e) s += bv[k * V + e] * sv[e];
     }
     s = row_sum<TG>(s);
-    if (g == 0 && m.row >= 0) y[m.row] = s;
+    if (g == 0 && m.row >= 0) {
+      if constexpr (WIN) {
+        const int line = m.row / winN;
+        y[(line % winW) * winN + (m.row - line * winN)] = s;
+        ((G<VT>*)yg)[m.row] = s;
+      } else {
+        y[m.row] = s;
+      }
+    }
   };
   if constexpr (sizeof(VT) == 4) {
     // FP32 (one buffer per table).  Level l starts with its off-block rows (av, ac), dense row
@@ -493,21 +505,35 @@ __device__ void trsv_general(const TriDev& T, const VT* in, VT* y, VT* sbuf) {
   }
 }
 
+// win: the LDS window of the triangular solves when y is in global memory (null: none)
 template <typename VT, bool YLDS, bool IN_GLOBAL, int OCC>
-__device__ __forceinline__ void trsv(const TriDev& T, int ka, int zidx, const VT* in, VT* y, VT* sbuf) {
+__device__ __forceinline__ void trsv(const TriDev& T, int ka, int zidx, const VT* in, VT* y, VT* sbuf, VT* win,
+                                     int zwin) {
+  L3<VT>* sl = (L3<VT>*)sbuf;
   if (YLDS && T.fast) {
     L3<VT>* yl = (L3<VT>*)y;
-    L3<VT>* sl = (L3<VT>*)sbuf;
     if (ka <= 2)
-      trsv_fast<VT, IN_GLOBAL, 2, OCC>(&T, zidx, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 2, OCC, false>(&T, zidx, in, yl, sl, nullptr);
     else if (ka <= 4)
-      trsv_fast<VT, IN_GLOBAL, 4, OCC>(&T, zidx, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 4, OCC, false>(&T, zidx, in, yl, sl, nullptr);
     else if (ka <= 8)
-      trsv_fast<VT, IN_GLOBAL, 8, OCC>(&T, zidx, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 8, OCC, false>(&T, zidx, in, yl, sl, nullptr);
     else if (ka <= 12)
-      trsv_fast<VT, IN_GLOBAL, 12, OCC>(&T, zidx, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 12, OCC, false>(&T, zidx, in, yl, sl, nullptr);
     else
-      trsv_fast<VT, IN_GLOBAL, 16, OCC>(&T, zidx, in, yl, sl);
+      trsv_fast<VT, IN_GLOBAL, 16, OCC, false>(&T, zidx, in, yl, sl, nullptr);
+  } else if (!YLDS && IN_GLOBAL && OCC == 1 && win && T.fast && T.winW > 0) {
+    L3<VT>* wl = (L3<VT>*)win;
+    if (ka <= 2)
+      trsv_fast<VT, true, 2, 1, true>(&T, zwin, in, wl, sl, y);
+    else if (ka <= 4)
+      trsv_fast<VT, true, 4, 1, true>(&T, zwin, in, wl, sl, y);
+    else if (ka <= 8)
+      trsv_fast<VT, true, 8, 1, true>(&T, zwin, in, wl, sl, y);
+    else if (ka <= 12)
+      trsv_fast<VT, true, 12, 1, true>(&T, zwin, in, wl, sl, y);
+    else
+      trsv_fast<VT, true, 16, 1, true>(&T, zwin, in, wl, sl, y);
   } else {
     trsv_general<VT, Build<OCC>::NT>(T, in, y, sbuf);
   }
@@ -634,7 +660,7 @@ __device__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, do
 // Buffers: y (nin^2 doubles, LDS first), s (>= max(nin^2 VT, n1^2 doubles)), d (nin^2 VT).
 template <typename VT, int MASK, int OCC>
 __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, const VT* r, VT* d, VT* y, VT* s,
-                       VT* sbuf, int ka, int zidx) {
+                       VT* sbuf, int ka, int zidx, VT* win, int zwin) {
   constexpr bool YL = MASK & kY;
   constexpr int NT = Build<OCC>::NT;
   const int n = I.ndof;
@@ -642,14 +668,14 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
   const TriDev& TL = OCC == 3 ? L.L8 : L.L;
   const TriDev& TU = OCC == 3 ? L.U8 : L.U;
   // step 1: pre-smoothing d = S r, then nu1 - 1 further steps d += S (r - A d)
-  trsv<VT, YL, true, OCC>(TL, ka, zidx, r, y, sbuf);
-  trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf);
+  trsv<VT, YL, true, OCC>(TL, ka, zidx, r, y, sbuf, win, zwin);
+  trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf, win, zwin);
   for (int i = threadIdx.x; i < n; i += NT) d[i] = y[i];
   __syncthreads();
   for (int m = 1; m < nu1; ++m) {
     apply_A<NT, VT, OCC>(I, L, d, r, s, y);
-    trsv<VT, YL, !(MASK & kS), OCC>(TL, ka, zidx, s, y, sbuf);
-    trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf);
+    trsv<VT, YL, !(MASK & kS), OCC>(TL, ka, zidx, s, y, sbuf, win, zwin);
+    trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf, win, zwin);
     for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
     __syncthreads();
   }
@@ -671,8 +697,8 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
   // step 5: nu2 post-smoothing steps d += S (r - A d)
   for (int m = 0; m < nu2; ++m) {
     apply_A<NT, VT, OCC>(I, L, d, r, s, y);
-    trsv<VT, YL, !(MASK & kS), OCC>(TL, ka, zidx, s, y, sbuf);
-    trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf);
+    trsv<VT, YL, !(MASK & kS), OCC>(TL, ka, zidx, s, y, sbuf, win, zwin);
+    trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf, win, zwin);
     for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
     __syncthreads();
   }
@@ -701,6 +727,9 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
   // the triangular solves read padding columns from the LDS word y[zidx], which stays zero, and
   // read sbuf (256 words) beyond a level's rows with zero coefficients: make it finite once
   if ((MASK & kY) && threadIdx.x == 0) y[plan.zidx] = (VT)0;
+  // window of the triangular solves when y is in global memory; its zero word likewise
+  VT* win = (!(MASK & kY) && plan.off_win >= 0) ? (VT*)(smem + plan.off_win) : nullptr;
+  if (win && threadIdx.x == 0) win[plan.zwin] = (VT)0;
   for (int i = threadIdx.x; i < 256; i += NT) sbuf[i] = (VT)0;
   double* Vl = P.vtab ? P.vtab[job.inst * kMaxLevels + job.level] : nullptr;
   const double* Gl = (P.gtab && job.level > 0) ? P.gtab[job.inst * kMaxLevels + job.level] : nullptr;
@@ -772,7 +801,7 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
         if (threadIdx.x == 0) atomicOr(P.status, 2);
         break;
       }
-      vcycle<VT, MASK, OCC>(I, L, P.nu1, P.nu2, r, d, y, s, sbuf, plan.ka, plan.zidx);
+      vcycle<VT, MASK, OCC>(I, L, P.nu1, P.nu2, r, d, y, s, sbuf, plan.ka, plan.zidx, win, plan.zwin);
       for (int i = threadIdx.x; i < n; i += NT) x[i] += (double)d[i];
       __syncthreads();
       ++cyc;

@@ -247,16 +247,17 @@ def test_autotune_same_result(torch, precision):
         assert torch.equal(U0, U1) and st0["vcycles"] == st1["vcycles"]
 
 
-@pytest.mark.parametrize("mask", [3 | 16, 1 | 16, 3])
-def test_forced_placement_same_result(torch, mask):
-    """Forced LDS placements, including the FP32 kernel build for two workgroups per CU (mask bit
-    16), compute the same arithmetic: bitwise the same trajectory and V-cycle count as the
-    default placement."""
-    name = "heat-p5-h64-Nt1024"
-    cfg = W.config(name)
-    cfg["instances"][0]["Nt"] = 64
-    cfg["instances"][0]["T"] = 1.0 / 16
-    say(f"case forced placement {mask} p=5 n=64 N_t=64")
+@pytest.mark.parametrize("mask,p,n", [(3 | 16, 5, 64), (1 | 16, 5, 64), (3, 5, 64), (2, 5, 64), (2, 3, 80)])
+def test_forced_placement_same_result(torch, mask, p, n):
+    """Forced LDS placements compute the same arithmetic: bitwise the same trajectory and V-cycle
+    count as the default placement.  Covers the FP32 kernel build for two workgroups per CU (mask
+    bit 16) and y in global memory (mask 2), where the triangular solves read the grid lines they
+    couple to from an LDS window.  At n = 80 the 81-row grid lines are split into two blocks, so
+    blocks straddle lines."""
+    cfg = W.config(f"heat-p{p}-h64-Nt1024")
+    d = cfg["instances"][0]
+    d["n"], d["Nt"], d["T"] = n, 64, 1.0 / 16
+    say(f"case forced placement {mask} p={p} n={n} N_t=64")
     S0 = make_solver(cfg, precision=1)
     (U0,), st0 = S0.solve_mgrit()
     S1 = make_solver(cfg, precision=1, lds_mask=mask)

@@ -145,3 +145,41 @@ def test_rejects_invalid_placement(kw):
                                 dict(lds_mask=15), dict(lds_mask=1)])
 def test_accepts_valid_placement(kw):
     host_solver(3, 6, **kw).close()
+
+
+def _block_levels(T, lower, bs, cap):
+    """Level count of bs-row blocks in dependency order, each at the first level after its
+    dependencies with room for its rows (cap rows per level, 0: no cap)."""
+    n = T.shape[0]
+    nb = (n + bs - 1) // bs
+    lev = np.zeros(nb, dtype=int)
+    used = []
+    for b in (range(nb) if lower else range(nb - 1, -1, -1)):
+        r0, r1 = b * bs, min(n, b * bs + bs)
+        deps = T.indices[T.indptr[r0]:T.indptr[r1]] // bs
+        deps = deps[deps != b]
+        lv = lev[deps].max() + 1 if len(deps) else 0
+        while cap and lv < len(used) and used[lv] + (r1 - r0) > cap:
+            lv += 1
+        if lv >= len(used):
+            used.extend([0] * (lv + 1 - len(used)))
+        used[lv] += r1 - r0
+        lev[b] = lv
+    return len(used), max(used)
+
+
+def test_schedule_levels_capped_at_row_slots():
+    """Grid lines split into 65-row blocks let the first block of a line run beside the last
+    blocks of the previous one: 130 rows, more than the 128 row slots of the prefetched triangular
+    solve.  The schedule then moves a block to a later level: at most 128 rows per level, every
+    block still after the blocks it depends on (the level count matches an independent greedy
+    placement)."""
+    p, n, bs = 2, 260, 65
+    S = host_solver(p, n, 0, trsv_block=bs, Nt=8)
+    L, U = S.host_matrix("L"), S.host_matrix("U")
+    for f, T, lower in ((0, L, True), (1, U, False)):
+        s = S.host_schedule(factor=f)
+        free_levels, free_rows = _block_levels(T, lower, bs, 0)
+        assert free_rows > 128  # the uncapped schedule would overflow the row slots
+        assert s["max_rows"] <= 128
+        assert s["levels"] == _block_levels(T, lower, bs, 128)[0] > free_levels
