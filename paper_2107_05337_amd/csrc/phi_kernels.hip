@@ -392,8 +392,8 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
       }
     }
   };
-  if constexpr (sizeof(VT) == 4) {
-    // FP32 (one buffer per table).  Level l starts with its off-block rows (av, ac), dense row
+  if constexpr (sizeof(VT) == 4 || OCC == 3) {
+    // FP32, and the 1024-thread build (one buffer per table).  Level l starts with its off-block rows (av, ac), dense row
     // (bv, xin) and broadcast metadata (C) loaded or in flight, and level l + 1's metadata record
     // in N.  Level l + 1's off-block rows are requested after phase A of level l, its dense row
     // after phase B; the scheduling barriers keep those requests where they are, so that each
@@ -425,7 +425,7 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
       lds_barrier();
     }
   } else {
-    // FP64 (dense rows twice as wide: two dense buffers, so that the next level's dense row
+    // FP64 with 512 threads (dense rows twice as wide: two dense buffers, so that the next level's dense row
     // streams in during phase A rather than holding up the barrier after phase B).  The loop is
     // unrolled by two: at even level l, M0 (broadcast), bv0, x0 and av/ac hold its data and M1
     // level l + 1's metadata record.
