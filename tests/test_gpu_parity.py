@@ -247,8 +247,9 @@ def test_autotune_same_result(torch, precision):
         assert torch.equal(U0, U1) and st0["vcycles"] == st1["vcycles"]
 
 
-@pytest.mark.parametrize("mask,p,n", [(3 | 16, 5, 64), (1 | 16, 5, 64), (3, 5, 64), (2, 5, 64), (2, 3, 80)])
-def test_forced_placement_same_result(torch, mask, p, n):
+@pytest.mark.parametrize("mask,p,n,precision", [(3 | 16, 5, 64, 1), (1 | 16, 5, 64, 1), (3, 5, 64, 1), (2, 5, 64, 1),
+                                                 (2, 3, 80, 1), (2, 5, 64, 0), (2, 3, 80, 0)])
+def test_forced_placement_same_result(torch, mask, p, n, precision):
     """Forced LDS placements compute the same arithmetic: bitwise the same trajectory and V-cycle
     count as the default placement.  Covers the FP32 kernel build for two workgroups per CU (mask
     bit 16) and y in global memory (mask 2), where the triangular solves read the grid lines they
@@ -257,10 +258,10 @@ def test_forced_placement_same_result(torch, mask, p, n):
     cfg = W.config(f"heat-p{p}-h64-Nt1024")
     d = cfg["instances"][0]
     d["n"], d["Nt"], d["T"] = n, 64, 1.0 / 16
-    say(f"case forced placement {mask} p={p} n={n} N_t=64")
-    S0 = make_solver(cfg, precision=1)
+    say(f"case forced placement {mask} p={p} n={n} N_t=64 precision {precision}")
+    S0 = make_solver(cfg, precision=precision)
     (U0,), st0 = S0.solve_mgrit()
-    S1 = make_solver(cfg, precision=1, lds_mask=mask)
+    S1 = make_solver(cfg, precision=precision, lds_mask=mask)
     gi = S1.group_info(0)
     say(f"  default {S0.group_info(0)['lds_mask']} forced {gi['lds_mask']} ({gi['lds_bytes']} B)")
     assert gi["lds_mask"] == mask
