@@ -1,6 +1,6 @@
 // phi_kernels.hip -- gfx950 kernels of the spatial solves and the MGRIT point updates.
 //
-// One workgroup (512 threads, eight 64-wide wavefronts) owns one right-hand side and runs the
+// One workgroup (512 or 1024 threads, see Build) owns one right-hand side and runs the
 // whole spatial solve Phi of Sec. 4 for it: right-hand side M u_k + dt f_{k+1}, FP64 residual,
 // p-multigrid V-cycles (ILUT smoothing, restriction to p = 1, exact p = 1 solve, prolongation)
 // until ||b - A x|| <= tol ||b||, and the MGRIT output (next point, or C-point residual).  A
@@ -13,7 +13,8 @@
 // applied by blocked level-scheduled triangular solves whose next level is prefetched into
 // registers while the current one computes; the workgroup then synchronises on LDS only.
 // Work vectors live in LDS when they fit (template MASK), else in a per-workgroup slice of
-// global scratch.
+// global scratch; when the triangular-solve vector y is in global memory, the solves read the
+// grid lines they couple to from an LDS window.
 #include <hip/hip_runtime.h>
 
 #include "device_types.hpp"
