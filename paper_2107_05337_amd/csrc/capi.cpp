@@ -564,10 +564,10 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
   TRY(upload_vals(H, dval, &T.dval));
   if (T.fast) {
     // slot tables: entry 0 reserved (empty slot / zero coefficient whose column is the LDS
-    // zero word); level l, row slot r at 1 + l * R + r.  Off-block rows: AS = ka * 4 entries in
+    // zero word); level l, row slot r at 1 + l * R + r.  Off-block rows: AS = ka * TG entries in
     // their natural order, zero-padded.  Dense rows: the columns from bq0 rounded down to 16
-    // bytes (zeros in front) in natural order, zero-padded to a multiple of four 16-byte units;
-    // bc = values per lane.  The kernel's lane g reads 16-byte units g, g + 4, ... of a row.
+    // bytes (zeros in front) in natural order, zero-padded to a multiple of TG 16-byte units;
+    // bc = values per lane.  The kernel's lane g of TG per row reads 16-byte units g, g + TG, ...
     const int R = std::max(1, S.max_rows), AS = RW, TGh = TG;
     const int V = H->fp32 ? 4 : 2;  // values per 16 bytes
     const size_t nslots = (size_t)(S.nlev + 2) * R + 1;
@@ -825,7 +825,7 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
         G.n1max = std::max(G.n1max, I.ndof1);
         G.maxrows = std::max(G.maxrows, inst_maxrows(I));
         // off-block entries per lane of the prefetched triangular solves: the widest ILUT row
-        // of the group's instances over the 4 lanes per row, rounded up to a power of two
+        // of the group's instances over the 4 (or 8) lanes per row, rounded up
         const int maxo = inst_max_offblock(I);
         // ka in {2, 4, 8, 12, 16}: 16-byte units of 4 entries per lane beyond 2
         auto ka_for = [](int need) { return need <= 2 ? 2 : std::min(16, (need + 3) / 4 * 4); };

@@ -6,7 +6,7 @@
 namespace pmg {
 
 constexpr int kMaxLevels = 12;   // MGRIT time levels per instance
-// Prefetched triangular-solve limits (the kernel runs 512 threads, 4 lanes per row slot): 128 row
+// Prefetched triangular-solve limits (512 threads with 4 lanes per row slot, or 1024 with 8): 128 row
 // slots per level, up to 64 off-block entries per row and dense diagonal blocks of up to 72 rows.
 constexpr int kRowSlots = 128;
 constexpr int kOffMax = 64;
@@ -20,8 +20,8 @@ struct Meta4 {
   int row;   // row (or -1 for an empty slot)
   int bo;    // offset of the row's dense values in dfast (a multiple of 16 bytes)
   int bqc;   // s position of the first dense column (low 16 bits, a multiple of 16 bytes' worth of
-             // values) | dense values per lane << 16 (the row holds 4 x that many, lane g reading
-             // 16-byte units g, g + 4, ...)
+             // values) | dense values per lane << 16 (the row holds TG x that many for TG lanes
+             // per row, lane g reading 16-byte units g, g + TG, ...)
   int na;    // off-block entries of the row (the rest of its AS-wide row is padding)
 };
 

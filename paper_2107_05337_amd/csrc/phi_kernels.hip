@@ -260,8 +260,8 @@ __device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t rs, int off, uns
   }
 }
 
-// Prefetched blocked triangular solve (one workgroup, 4 lanes per row, up to kRowSlots rows per
-// level).  Per level: phase A forms s_i = in_i - sum of the row's off-block entries times y
+// Prefetched blocked triangular solve (one workgroup, TG = 4 or 8 lanes per row, up to kRowSlots
+// rows per level).  Per level: phase A forms s_i = in_i - sum of the row's off-block entries times y
 // (finished levels), phase B multiplies s by the row's part of the dense diagonal-block inverse.
 // The tables of level l + 1 stream in while level l computes: its off-block rows are requested
 // right after phase A of level l, its dense rows (and the slot metadata of level l + 2) right
@@ -315,7 +315,7 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
     m.bqc = __builtin_amdgcn_mov_dpp(m.bqc, 0x00, 0xF, 0xF, true);
     m.na = __builtin_amdgcn_mov_dpp(m.na, 0x00, 0xF, 0xF, true);
   };
-  // off-block row of slot (l, r) at RW + (l * R + r) * RW: lane g reads units g, g + 4, ... of
+  // off-block row of slot (l, r) at RW + (l * R + r) * RW: lane g reads units g, g + TG, ... of
   // WA entries, those past the row's na entries read as zeros
   auto load_a = [&](int l, const Meta4& m, VT* av, int* ac) {
     const int base = RW + (l * R + r) * RW;
@@ -336,7 +336,7 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
       }
     }
   };
-  // dense row at m.bo: lane g reads units g, g + 4, ... (bc values per lane, zeros past them),
+  // dense row at m.bo: lane g reads units g, g + TG, ... (bc values per lane, zeros past them),
   // and lane 0 of the quad the row's right-hand side
   auto load_b = [&](const Meta4& m, VT* bv, VT& xin) {
     // the right-hand side first: phase A needs it before phase B needs the dense row
