@@ -173,6 +173,79 @@ __device__ __forceinline__ double pass_y(int ncols, int nin, const BandDev& Bd, 
   return part;
 }
 
+// Both first-direction passes of A_l at once (bands of equal shape): t1 = X1 pass, t2 = Mx2 pass
+// of the same input, each tap of the input read once for both.
+template <int NT, typename AT, typename IT, typename OT>
+__device__ __forceinline__ void pass_x2(int nrows, int nin, const BandDev& B1d, const BandDev& B2d, const IT* in,
+                                        OT* out1, OT* out2) {
+  const G<AT>* __restrict__ B1 = band_ptr<AT>(B1d);
+  const G<AT>* __restrict__ B2 = band_ptr<AT>(B2d);
+  const int nout = B1d.rows, w = B1d.w, lo = B1d.lo;
+  const int groups = NT / nout;
+  const int o = threadIdx.x % nout, g = threadIdx.x / nout;
+  if (g >= groups) return;
+  AT b1[kBandMax], b2[kBandMax];
+  int jj[kBandMax];
+#pragma unroll
+  for (int d = 0; d < kBandMax; ++d) {
+    b1[d] = d < w ? B1[o * w + d] : (AT)0;
+    b2[d] = d < w ? B2[o * w + d] : (AT)0;
+    const int j = o + lo + d;
+    jj[d] = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+  }
+  for (int r = g; r < nrows; r += groups) {
+    const IT* src = in + r * nin;
+    AT s1 = 0, s2 = 0;
+#pragma unroll
+    for (int d = 0; d < kBandMax; ++d) {
+      const AT v = (AT)src[jj[d]];
+      s1 += b1[d] * v;
+      s2 += b2[d] * v;
+    }
+    out1[r * nout + o] = (OT)s1;
+    out2[r * nout + o] = (OT)s2;
+  }
+}
+
+// Both second-direction passes at once: out = a1 (B1 pass of T1) + a2 (B2 pass of T2) + beta z,
+// bands of equal shape.  Returns this thread's share of sum out^2.
+template <int NT, typename AT, typename TT, typename ZT, typename OT>
+__device__ __forceinline__ double pass_y2(int ncols, int nin, const BandDev& B1d, const BandDev& B2d, const TT* T1,
+                                          const TT* T2, AT a1, AT a2, const ZT* z, AT beta, OT* out) {
+  const G<AT>* __restrict__ B1 = band_ptr<AT>(B1d);
+  const G<AT>* __restrict__ B2 = band_ptr<AT>(B2d);
+  const int nout = B1d.rows, w = B1d.w, lo = B1d.lo;
+  const int tot = nout * ncols;
+  double part = 0.0;
+  for (int t = threadIdx.x; t < tot; t += NT) {
+    const int o = t / ncols, c = t - o * ncols;
+    const G<AT>* b1 = B1 + o * w;
+    const G<AT>* b2 = B2 + o * w;
+    AT c1[kBandMax], c2[kBandMax];
+#pragma unroll
+    for (int d = 0; d < kBandMax; ++d) {
+      c1[d] = b1[d < w ? d : w - 1];
+      c2[d] = b2[d < w ? d : w - 1];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    AT s1 = 0, s2 = 0;
+#pragma unroll
+    for (int d = 0; d < kBandMax; ++d) {
+      int j = o + lo + d;
+      j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+      if (d < w) {
+        s1 += c1[d] * (AT)T1[j * ncols + c];
+        s2 += c2[d] * (AT)T2[j * ncols + c];
+      }
+    }
+    AT v = a1 * s1 + a2 * s2;
+    if (z) v += beta * (AT)z[t];
+    out[t] = (OT)v;
+    part += (double)v * (double)v;
+  }
+  return part;
+}
+
 // out = beta z - A_l x with A_l = My (x) X1 + c Ky (x) Mx2 (temp: nin x nin scratch, may not
 // alias x or out).  Returns this thread's share of ||out||^2.
 // (OCC only separates the instances called from the two-workgroups-per-CU kernels, which get
@@ -180,6 +253,20 @@ __device__ __forceinline__ double pass_y(int ncols, int nin, const BandDev& Bd, 
 template <int NT, typename AT, int OCC = 1, typename XT, typename ZT, typename OT, typename TT>
 __device__ double apply_A(const InstDev& I, const LevelDev& L, const XT* x, const ZT* z, OT* out, TT* tmp) {
   const int n = I.nin;
+  if constexpr (sizeof(TT) == 4) {
+    // FP32 temporaries: tmp is an FP64-sized slot and holds both, so the two terms of A_l take
+    // one first- and one second-direction pass
+    if (L.X1.w == I.Mx2.w && L.X1.lo == I.Mx2.lo && I.My.w == I.Ky.w && I.My.lo == I.Ky.lo &&
+        L.X1.w <= kBandMax && I.My.w <= kBandMax && I.Mx2.rows <= NT) {
+      TT* t2 = tmp + n * n;
+      pass_x2<NT, AT>(n, n, L.X1, I.Mx2, x, tmp, t2);
+      __syncthreads();
+      const double part =
+          pass_y2<NT, AT>(n, n, I.My, I.Ky, tmp, (const TT*)t2, (AT)-1, (AT)(-L.c), z, (AT)1, out);
+      __syncthreads();
+      return part;
+    }
+  }
   pass_x<NT, AT>(n, n, L.X1, x, tmp);
   __syncthreads();
   pass_y<NT, AT>(n, n, I.My, tmp, (AT)-1, z, (AT)1, false, nullptr, nullptr, out);
