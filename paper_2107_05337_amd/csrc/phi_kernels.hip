@@ -207,8 +207,9 @@ __device__ __forceinline__ void pass_x2(int nrows, int nin, const BandDev& B1d, 
   }
 }
 
-// Both second-direction passes at once: out = a1 (B1 pass of T1) + a2 (B2 pass of T2) + beta z,
-// bands of equal shape.  Returns this thread's share of sum out^2.
+// Both second-direction passes at once: out = (a1 (B1 pass of T1) + beta z) + a2 (B2 pass of T2),
+// bands of equal shape, rounded in the same order as two pass_y calls (the second accumulating),
+// so fused and unfused residuals agree bitwise.  Returns this thread's share of sum out^2.
 template <int NT, typename AT, typename TT, typename ZT, typename OT>
 __device__ __forceinline__ double pass_y2(int ncols, int nin, const BandDev& B1d, const BandDev& B2d, const TT* T1,
                                           const TT* T2, AT a1, AT a2, const ZT* z, AT beta, OT* out) {
@@ -233,13 +234,12 @@ __device__ __forceinline__ double pass_y2(int ncols, int nin, const BandDev& B1d
     for (int d = 0; d < kBandMax; ++d) {
       int j = o + lo + d;
       j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
-      if (d < w) {
-        s1 += c1[d] * (AT)T1[j * ncols + c];
-        s2 += c2[d] * (AT)T2[j * ncols + c];
-      }
+      s1 += (d < w ? c1[d] : (AT)0) * (AT)T1[j * ncols + c];
+      s2 += (d < w ? c2[d] : (AT)0) * (AT)T2[j * ncols + c];
     }
-    AT v = a1 * s1 + a2 * s2;
+    AT v = a1 * s1;
     if (z) v += beta * (AT)z[t];
+    v += a2 * s2;
     out[t] = (OT)v;
     part += (double)v * (double)v;
   }
@@ -871,13 +871,31 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
     for (; bn2 != 0.0;) {
       // FP64 residual r = b - A x (stored in the V-cycle precision) and its norm
       part = 0.0;
-      if constexpr (sizeof(VT) == 8) {
-        part = apply_A<NT, double, OCC>(I, L, x, b, r, yd);
-      } else {
-        // residual in FP64 through the FP64 temp, then rounded into r
-        double* rr = (double*)(ws + 5 * nm);  // FP64 residual staging in global scratch
-        part = apply_A<NT, double, OCC>(I, L, x, b, rr, yd);
-        for (int i = threadIdx.x; i < n; i += NT) r[i] = (VT)rr[i];
+      // Fused form (one first- and one second-direction pass, written straight into r) where LDS
+      // holds a second FP64 temporary of n values: the d and s slots (FP32, contiguous) or the
+      // d slot (FP64), both free here.  Elsewhere the four-pass form, which rounds the same way.
+      constexpr bool FUSE = sizeof(VT) == 8 ? (MASK & kD) != 0 : ((MASK & kD) && (MASK & kS));
+      bool fused = false;
+      if constexpr (FUSE) {
+        if (L.X1.w == I.Mx2.w && L.X1.lo == I.Mx2.lo && I.My.w == I.Ky.w && I.My.lo == I.Ky.lo &&
+            L.X1.w <= kBandMax && I.My.w <= kBandMax && I.Mx2.rows <= NT) {
+          double* t2 = (double*)(smem + plan.off_d);
+          pass_x2<NT, double>(I.nin, I.nin, L.X1, I.Mx2, x, yd, t2);
+          __syncthreads();
+          part = pass_y2<NT, double>(I.nin, I.nin, I.My, I.Ky, yd, (const double*)t2, -1.0, -L.c, b, 1.0, r);
+          __syncthreads();
+          fused = true;
+        }
+      }
+      if (!fused) {
+        if constexpr (sizeof(VT) == 8) {
+          part = apply_A<NT, double, OCC>(I, L, x, b, r, yd);
+        } else {
+          // residual in FP64 through the FP64 temp, then rounded into r
+          double* rr = (double*)(ws + 5 * nm);  // FP64 residual staging in global scratch
+          part = apply_A<NT, double, OCC>(I, L, x, b, rr, yd);
+          for (int i = threadIdx.x; i < n; i += NT) r[i] = (VT)rr[i];
+        }
       }
       const double rn2 = block_sum<NT>(part, red);
       if (!(rn2 <= 1.0e300)) {  // NaN or Inf
