@@ -91,8 +91,9 @@ typedef struct {
  * pmgrit_net_load before solving).  With guess 3, sequential stepping predicts every step;
  * MGRIT predicts the level-0 F- and C-relaxation steps of its first iteration, step by step, and
  * uses guess 2 afterwards.
- * trsv_block: row-block size of the blocked triangular solves (0 = autotune,
- * 1 = plain row level-scheduling, -1 = one grid line). */
+ * trsv_block: row-block size of the blocked triangular solves (0 = blocks of 64 consecutive
+ * rows, the default; 1 = plain row level-scheduling; -1 = one grid line per block, split evenly
+ * above 72 rows; k >= 2 = blocks of k rows). */
 typedef struct {
   int32_t nu1, nu2;       /* pre-/post-smoothing steps (>= 1) */
   double ilut_droptol;    /* ILUT drop tolerance tau (relative to the row 2-norm) */

@@ -140,7 +140,7 @@ def _dptr(t):
 
 def default_solver_opts(**kw) -> SolverOpts:
     o = SolverOpts(nu1=1, nu2=1, ilut_droptol=1e-12, ilut_fill=0, spatial_tol=1e-12, max_vcycles=100, precision=0,
-                   guess=2, trsv_block=-1, autotune=0, coarse_tol=0.0, lds_mask=0)
+                   guess=2, trsv_block=0, autotune=0, coarse_tol=0.0, lds_mask=0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o

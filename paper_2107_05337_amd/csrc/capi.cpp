@@ -342,7 +342,12 @@ static pmgrit_status setup_level(const pmgrit_handle* H, InstHost& I, int l, std
   }
   if (!ilut(Lv.A, H->so.ilut_droptol, lc, uc, Lv.L, Lv.U, err)) return PMGRIT_E_FACTOR;
   int bs = H->so.trsv_block;
-  if (bs == 0 || bs == -1) {
+  if (bs == 0) {
+    // 64 consecutive rows per block, whatever the grid lines: four full wavefronts of the
+    // 512-thread build per level (a 65-row line would leave a fifth wavefront nearly empty, and
+    // the level waits for it), and lines shorter than 64 rows share blocks, so fewer levels
+    bs = std::min(I.ndof, kWaveBlock);
+  } else if (bs == -1) {
     // one grid line per block, split evenly when a line exceeds the prefetched path's 72 rows
     const int parts = (I.Nin + kDenseMax - 1) / kDenseMax;
     bs = (I.Nin + parts - 1) / parts;

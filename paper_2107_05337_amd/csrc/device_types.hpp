@@ -14,6 +14,8 @@ constexpr int kOffMax = 64;
 // bytes (every table of that path is smaller); an offset at or past it reads zeros
 constexpr unsigned kBufBytes = 0x7ffff000u;
 constexpr int kDenseMax = 72;
+// default row-block size of the triangular solves
+constexpr int kWaveBlock = 64;
 
 // per (level, row slot) metadata of the prefetched triangular solve
 struct Meta4 {

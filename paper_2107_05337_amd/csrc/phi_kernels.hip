@@ -283,8 +283,8 @@ __device__ double apply_A(const InstDev& I, const LevelDev& L, const XT* x, cons
 // ---------------------------------------------------------------------------------------
 
 // Both paths solve T y = in (T = L with unit diagonal, or U), writing y (which may alias in),
-// level by level over a blocked level schedule (blocks = grid lines, split to at most
-// kDenseMax rows; a level is a set of independent blocks).
+// level by level over a blocked level schedule (blocks of consecutive rows, at most kDenseMax;
+// a level is a set of independent blocks).
 template <class T>
 using L3 = __attribute__((address_space(3))) T;
 

@@ -34,7 +34,7 @@ def torch():
     return T
 
 
-def make_solver(cfg, precision=0, guess=2, trsv_block=-1, tol=1e-10, stol=1e-12, autotune=0, ctol=0.0, lds_mask=0,
+def make_solver(cfg, precision=0, guess=2, trsv_block=0, tol=1e-10, stol=1e-12, autotune=0, ctol=0.0, lds_mask=0,
                 **mo):
     probs = [pm.problem(d["p"], d["n"], d["Nt"], kappa=d["kappa"], T=d["T"], domain=d["domain"])
              for d in cfg["instances"]]
@@ -64,7 +64,8 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("p,n,domain,precision,blk", [
-    (2, 8, 0, 0, -1), (3, 12, 0, 0, 1), (3, 12, 1, 0, -1), (4, 10, 0, 1, -1), (2, 16, 1, 1, 1), (5, 9, 0, 0, 7)])
+    (2, 8, 0, 0, -1), (3, 12, 0, 0, 1), (3, 12, 1, 0, -1), (4, 10, 0, 1, -1), (2, 16, 1, 1, 1), (5, 9, 0, 0, 7),
+    (3, 12, 1, 0, 0), (4, 10, 0, 1, 0), (5, 70, 0, 0, 0), (3, 62, 0, 1, 0)])
 def test_phi_matches_dense_solve(torch, p, n, domain, precision, blk):
     say(f"case phi p={p} n={n} domain={domain} precision={precision} block={blk}")
     cfg = W.small("x", p, n, 16, domain=domain)

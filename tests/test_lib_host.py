@@ -116,6 +116,22 @@ def test_schedules():
         assert s["levels"] == nin and s["max_rows"] == nin
 
 
+@pytest.mark.parametrize("p,n", [(3, 12), (2, 70), (5, 9)])
+def test_default_schedule_blocks_of_64_rows(p, n):
+    """The default blocking takes 64 consecutive rows per block whatever the grid lines (the whole
+    system when it is smaller), placed in dependency order: the level counts match an independent
+    greedy placement of the same blocks, and no level holds more than 128 rows."""
+    S = host_solver(p, n, 0, trsv_block=0, Nt=8)
+    L, U = S.host_matrix("L"), S.host_matrix("U")
+    ndof = (n + p - 2) ** 2
+    bs = min(64, ndof)
+    for f, T, lower in ((0, L, True), (1, U, False)):
+        s = S.host_schedule(factor=f)
+        assert s["block_size"] == bs and s["blocks"] == (ndof + bs - 1) // bs
+        levels, rows = _block_levels(T, lower, bs, 128)
+        assert s["levels"] == levels and s["max_rows"] == rows <= 128
+
+
 def test_invalid_arguments_rejected():
     with pytest.raises(pm.PmgritError) as e:
         host_solver(1, 8)
