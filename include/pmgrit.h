@@ -114,8 +114,12 @@ typedef struct {
                            * choice).  Otherwise the placement of every launch group: bits 1 y,
                            * 2 d, 4 s, 8 x select the work vectors kept in LDS; 16 (precision 1
                            * with bit 1 and without 4 and 8) selects the kernel build for two
-                           * workgroups per CU.  Results do not depend on it.  PMGRIT_E_ARG if it
-                           * does not fit a group's LDS or is combined with autotune. */
+                           * workgroups per CU; 32 (with bit 1) the 1024-thread build and 64 (with
+                           * bit 1, at most 64 rows per triangular-solve level) the 512-thread
+                           * build, both with 8 lanes per triangular-solve row.  Results do not
+                           * depend on bits 1-16; the 8-lane builds sum each triangular-solve row in
+                           * another order (rounding only).  PMGRIT_E_ARG if it does not fit a
+                           * group's LDS or its rows, or is combined with autotune. */
 } pmgrit_solver_opts;
 
 typedef struct {

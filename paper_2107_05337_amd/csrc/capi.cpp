@@ -844,9 +844,12 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
       lds_plan(G.nmax, G.n1max, G.maxrows, vt, G.ka, dev_lds, G.winw, G.mask, G.lds_bytes, G.plan);
       if (H->so.lds_mask) {  // placement chosen by the caller
         int bytes = 0;
-        const LdsPlan plan = lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, (H->so.lds_mask & kT1024) ? G.ka8 : G.ka,
-                                           dev_lds, G.winw, H->so.lds_mask, bytes);
+        const LdsPlan plan = lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt,
+                                           (H->so.lds_mask & (kT1024 | kW8)) ? G.ka8 : G.ka, dev_lds, G.winw,
+                                           H->so.lds_mask, bytes);
         if (bytes == 0) return fail(PMGRIT_E_ARG, "lds_mask does not fit a launch group's LDS");
+        if ((H->so.lds_mask & kW8) && G.maxrows > kRowSlots / 2)
+          return fail(PMGRIT_E_ARG, "lds_mask 64 needs at most 64 rows per triangular-solve level");
         G.mask = H->so.lds_mask;
         G.lds_bytes = bytes;
         G.plan = plan;
@@ -1233,11 +1236,13 @@ static pmgrit_status autotune(pmgrit_handle* H) {
     // fastest placement for a probe of n right-hand sides
     auto probe = [&](int n, int& best_mask, int& best_bytes, LdsPlan& best_plan, float& best_ms) -> hipError_t {
       best_ms = 1e30f;
-      for (int mk : {15, 7, 3, 1, 3 | kOcc2, 1 | kOcc2, 15 | kT1024, 7 | kT1024, 3 | kT1024, 1 | kT1024}) {
+      for (int mk : {15, 7, 3, 1, 3 | kOcc2, 1 | kOcc2, 15 | kT1024, 7 | kT1024, 3 | kT1024, 1 | kT1024, 15 | kW8,
+                     7 | kW8, 3 | kW8, 1 | kW8}) {
         if ((mk & kOcc2) && !H->fp32) continue;
+        if ((mk & kW8) && G.maxrows > kRowSlots / 2) continue;
         int bytes = 0;
-        const LdsPlan plan =
-            lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, (mk & kT1024) ? G.ka8 : G.ka, dev_lds, G.winw, mk, bytes);
+        const LdsPlan plan = lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, (mk & (kT1024 | kW8)) ? G.ka8 : G.ka,
+                                           dev_lds, G.winw, mk, bytes);
         if (bytes == 0 || ((mk & kOcc2) && 2 * bytes > dev_lds)) continue;
         hipError_t e = phi_prepare(H->fp32, mk, bytes);
         if (e != hipSuccess) return e;
@@ -1263,7 +1268,7 @@ static pmgrit_status autotune(pmgrit_handle* H) {
         }
         // the 512-thread build is kept unless another build is at least 3 % faster on the probe
         // (they are often within the probe's noise, and this keeps the choice stable)
-        const bool special = mk & (kOcc2 | kT1024), best_special = best_mask & (kOcc2 | kT1024);
+        const bool special = mk & (kOcc2 | kT1024 | kW8), best_special = best_mask & (kOcc2 | kT1024 | kW8);
         const float margin = special == best_special ? 1.f : special ? 0.97f : 1.f / 0.97f;
         if (ms < best_ms * margin) {
           best_ms = ms;
@@ -1316,8 +1321,9 @@ pmgrit_status pmgrit_create(int32_t n_instances, const pmgrit_problem* probs, co
   if (so.nu1 < 1 || so.nu2 < 0 || !(so.ilut_droptol >= 0) || !(so.spatial_tol > 0) || so.max_vcycles < 1 ||
       (so.precision != 0 && so.precision != 1) || so.guess < 0 || so.guess > 3 || so.trsv_block < -1 ||
       so.autotune < 0 || so.autotune > 1 || !(so.coarse_tol >= 0) || so.coarse_tol >= 1 || so.lds_mask < 0 ||
-      so.lds_mask > 63 || (so.lds_mask && so.autotune) ||
+      so.lds_mask > 127 || (so.lds_mask && so.autotune) ||
       ((so.lds_mask & kT1024) && ((so.lds_mask & kOcc2) || !(so.lds_mask & kY))) ||
+      ((so.lds_mask & kW8) && ((so.lds_mask & (kOcc2 | kT1024)) || !(so.lds_mask & kY))) ||
       ((so.lds_mask & kOcc2) && (so.precision != 1 || (so.lds_mask & 15) != ((so.lds_mask & 15) & (kY | kD)) ||
                                  !(so.lds_mask & kY))))
     return fail(PMGRIT_E_ARG, "invalid solver options");

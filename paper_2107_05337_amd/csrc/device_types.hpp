@@ -135,5 +135,9 @@ constexpr int kOcc2 = 16;
 // placement flag: the spatial-solve kernel built for 1024-thread workgroups (8 lanes per
 // triangular-solve row, slot tables in that layout); y must be in LDS
 constexpr int kT1024 = 32;
+// placement flag: the 512-thread spatial-solve kernel with 8 lanes per triangular-solve row (the
+// 1024-thread build's slot tables, 64 row slots); y must be in LDS and every level of the
+// group's schedules must hold at most 64 rows
+constexpr int kW8 = 64;
 
 }  // namespace pmg

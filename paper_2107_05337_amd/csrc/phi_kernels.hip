@@ -34,10 +34,11 @@ __device__ __forceinline__ const G<T>* gp(const T* p) {
 // Kernel builds: OCC 1 runs 512 threads (4 lanes per triangular-solve row, 128 row slots per
 // level, a 256-register budget per thread), OCC 2 the same limited to 128 registers (two
 // workgroups per CU), OCC 3 1024 threads (8 lanes per row, 128 registers): shorter per-lane
-// work in every phase of one solve.
+// work in every phase of one solve.  OCC 4 runs 512 threads with 8 lanes per row (64 row slots
+// per level, 256 registers), for schedules of at most 64 rows per level.
 template <int OCC>
 struct Build {
-  static constexpr int NT = OCC == 3 ? 1024 : 512, TG = NT / kRowSlots;
+  static constexpr int NT = OCC == 3 ? 1024 : 512, TG = (OCC == 3 || OCC == 4) ? 8 : 4;
 };
 
 template <int G, typename T>
@@ -753,8 +754,8 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
   constexpr int NT = Build<OCC>::NT;
   const int n = I.ndof;
   // the 1024-thread build reads the factors' slot tables laid out for 8 lanes per row
-  const TriDev& TL = OCC == 3 ? L.L8 : L.L;
-  const TriDev& TU = OCC == 3 ? L.U8 : L.U;
+  const TriDev& TL = Build<OCC>::TG == 8 ? L.L8 : L.L;
+  const TriDev& TU = Build<OCC>::TG == 8 ? L.U8 : L.U;
   // step 1: pre-smoothing d = S r, then nu1 - 1 further steps d += S (r - A d)
   trsv<VT, YL, true, OCC>(TL, ka, zidx, r, y, sbuf, win, zwin);
   trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf, win, zwin);
@@ -1001,6 +1002,11 @@ template <typename VT, int MASK>
 __global__ void __launch_bounds__(1024) phi_kernel_t(PhiParams P, LdsPlan plan) {
   phi_body<VT, MASK, 3>(P, plan);
 }
+// the 512-thread build with 8 lanes per triangular-solve row (placement flag kW8)
+template <typename VT, int MASK>
+__global__ void __launch_bounds__(512) phi_kernel_w8(PhiParams P, LdsPlan plan) {
+  phi_body<VT, MASK, 4>(P, plan);
+}
 
 using PhiFn = void (*)(PhiParams, LdsPlan);
 
@@ -1012,6 +1018,14 @@ static PhiFn pick(int mask) {
       case 7: return phi_kernel_t<VT, 7>;
       case 3: return phi_kernel_t<VT, 3>;
       default: return phi_kernel_t<VT, 1>;
+    }
+  }
+  if (mask & kW8) {
+    switch (mask & 15) {
+      case 15: return phi_kernel_w8<VT, 15>;
+      case 7: return phi_kernel_w8<VT, 7>;
+      case 3: return phi_kernel_w8<VT, 3>;
+      default: return phi_kernel_w8<VT, 1>;
     }
   }
   if constexpr (sizeof(VT) == 4) {

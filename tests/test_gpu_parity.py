@@ -239,9 +239,9 @@ def test_autotune_same_result(torch, precision):
     say(f"  default {S0.group_info(0)['lds_mask']} tuned {gi['lds_mask']} ({gi['lds_bytes']} B)")
     (U1,), st1 = S1.solve_mgrit()
     assert gi["lds_mask"] & 1
-    if (gi["lds_mask"] | gi["lds_mask_wide"]) & 32:
-        # a 1024-thread build sums rows over 8 lanes and the workgroup over 16 waves: the same
-        # solves up to rounding
+    if (gi["lds_mask"] | gi["lds_mask_wide"]) & (32 | 64):
+        # the 8-lanes-per-row builds sum each triangular-solve row in another order (and the
+        # 1024-thread one the workgroup over 16 waves): the same solves up to rounding
         assert rel(U1.cpu().numpy(), U0.cpu().numpy()) <= 1e-11
         assert abs(st1["vcycles"] - st0["vcycles"]) <= 0.02 * st0["vcycles"]
     else:
@@ -270,10 +270,12 @@ def test_forced_placement_same_result(torch, mask, p, n, precision):
     assert torch.equal(U0, U1) and st0["vcycles"] == st1["vcycles"]
 
 
-@pytest.mark.parametrize("precision,mask", [(1, 15 | 32), (0, 15 | 32), (1, 1 | 32)])
+@pytest.mark.parametrize("precision,mask", [(1, 15 | 32), (0, 15 | 32), (1, 1 | 32), (1, 15 | 64), (0, 15 | 64),
+                                            (1, 1 | 64), (0, 3 | 64)])
 def test_1024_thread_build(torch, precision, mask):
-    """The 1024-thread kernel build (8 lanes per triangular-solve row, slot tables in that layout)
-    reaches the oracle's sequential implicit Euler to the same 1e-10 as the default build."""
+    """The kernel builds with 8 lanes per triangular-solve row (slot tables in that layout): 1024
+    threads (mask bit 32) and 512 threads with 64 row slots (bit 64) reach the oracle's sequential
+    implicit Euler to the same 1e-10 as the default build."""
     name = "heat-p5-h64-Nt1024"
     cfg = W.config(name)
     d = cfg["instances"][0]
@@ -309,3 +311,18 @@ def test_coarse_tolerance(torch, precision):
     say(f"  iters {st['mgrit_iters']} (oracle {r['iters']}), V-cycles {st['vcycles']} vs {st0['vcycles']} at 1e-12")
     assert abs(st["mgrit_iters"] - r["iters"]) <= 1
     assert st["vcycles"] < st0["vcycles"]
+
+
+def test_w8_build_needs_64_row_levels(torch):
+    """The 512-thread 8-lane build has 64 row slots: with one grid line of 67 rows per block (p = 5,
+    n = 64) the forced placement is refused at create, and the autotuner leaves that build out."""
+    cfg = W.config("heat-p5-h64-Nt1024")
+    cfg["instances"][0]["Nt"] = 16
+    say("case 8-lane 512-thread build with 67-row levels")
+    with pytest.raises(pm.PmgritError) as e:
+        make_solver(cfg, trsv_block=-1, lds_mask=15 | 64)
+    assert e.value.code == -1
+    S = make_solver(cfg, trsv_block=-1, autotune=1)
+    gi = S.group_info(0)
+    assert not ((gi["lds_mask"] | gi["lds_mask_wide"]) & 64)
+    S.close()

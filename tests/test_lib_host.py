@@ -149,16 +149,20 @@ def test_invalid_arguments_rejected():
 
 @pytest.mark.parametrize("kw", [dict(lds_mask=-1), dict(lds_mask=32), dict(lds_mask=3, autotune=1),
                                 dict(lds_mask=3 | 16, precision=0), dict(lds_mask=7 | 16, precision=1),
-                                dict(lds_mask=2 | 16, precision=1)])
+                                dict(lds_mask=2 | 16, precision=1), dict(lds_mask=64), dict(lds_mask=2 | 64),
+                                dict(lds_mask=1 | 16 | 64, precision=1), dict(lds_mask=1 | 32 | 64),
+                                dict(lds_mask=128)])
 def test_rejects_invalid_placement(kw):
-    """The forced LDS placement is checked at create: in range, not with the autotuner, and the
-    two-workgroups-per-CU build only in precision 1 with y (and at most d) in LDS."""
+    """The forced LDS placement is checked at create: in range, not with the autotuner, the
+    two-workgroups-per-CU build only in precision 1 with y (and at most d) in LDS, the 8-lane
+    builds only with y in LDS and one at a time."""
     with pytest.raises(pm.PmgritError):
         host_solver(3, 6, **kw)
 
 
 @pytest.mark.parametrize("kw", [dict(lds_mask=3 | 16, precision=1), dict(lds_mask=1 | 16, precision=1),
-                                dict(lds_mask=15), dict(lds_mask=1)])
+                                dict(lds_mask=15), dict(lds_mask=1), dict(lds_mask=15 | 64), dict(lds_mask=1 | 64),
+                                dict(lds_mask=15 | 32)])
 def test_accepts_valid_placement(kw):
     host_solver(3, 6, **kw).close()
 
