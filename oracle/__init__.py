@@ -20,6 +20,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
 _llp = C.POINTER(C.c_longlong)
+FN2 = C.CFUNCTYPE(C.c_double, C.c_double, C.c_double)  # a function of the physical coordinates (x, y)
 
 
 def build(force: bool = False) -> str:
@@ -27,7 +28,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+            ["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _SRC, "-lm"]
         )
         os.replace(tmp, _LIB)
     return _LIB
@@ -64,14 +65,24 @@ def lib():
         L.orc_project.argtypes = [C.c_void_p, C.c_int, _ip, _ip, _dp, _dp]
         L.orc_ilut.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, _ip]
         L.orc_ilut_get.argtypes = [_ip, _ip, _dp, _ip, _ip, _dp]
-        L.orc_pmg_solve.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
-                                    C.c_double, C.c_int, _dp, _dp, _ip]
+        L.orc_pmg_solve.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                                    C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _ip]
         L.orc_sequential.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, _dp, C.c_int, _dp, _dp]
-        L.orc_sequential_pmg.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, _dp, C.c_int, _dp,
-                                         C.c_double, C.c_double, C.c_int, _dp, _llp]
-        L.orc_mgrit.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, _dp, C.c_int, _dp,
-                                C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, C.c_double,
-                                C.c_double, C.c_int, C.c_int, _dp, _ip, _llp, _llp, _dp]
+        L.orc_sequential_theta.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, _dp, C.c_int, C.c_double,
+                                           _dp, _dp]
+        L.orc_sequential_pmg.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, _dp, C.c_int, C.c_double, _dp,
+                                         C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _llp]
+        L.orc_mgrit.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, _dp, C.c_int, _dp, _ip, _dp, _dp, _ip,
+                                _llp, _llp, _dp]
+        L.orc_load_vector_fn.argtypes = [C.c_void_p, FN2, _dp]
+        L.orc_l2_error_fn.argtypes = [C.c_void_p, _dp, FN2]
+        L.orc_l2_error_fn.restype = C.c_double
+        L.orc_hmg_info.argtypes = [C.c_void_p, _ip]
+        L.orc_hmg_matrix.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, _ip, _ip, _ip,
+                                     _dp]
+        L.orc_hmg_cycles.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int, _dp, _dp]
+        L.orc_gs_sweep.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int, _dp, _dp]
+        L.orc_gs_sweep.restype = None
         _lib = L
     return _lib
 
@@ -220,36 +231,88 @@ class Problem:
         return rc, L, U
 
     def pmg_solve(self, kappa: float, dt: float, b: np.ndarray, x0=None, tau=1e-12, nu1=1, nu2=1,
-                  tol=1e-12, maxcyc=100):
+                  tol=1e-12, maxcyc=100, theta=1.0, prec=0, coarse=0, solver=0, unlimited=False):
+        """Spatial solve of (M + theta kappa dt K) x = b from x0.  solver 0: p-multigrid (prec 1: FP32
+        V-cycle in FP64 refinement; coarse 0: exact p = 1 solve, 1: one h-multigrid W-cycle); solver 1:
+        Jacobi-preconditioned CG.  unlimited: ILUT without per-row caps.  Returns (rc, x, cycles)."""
         b = np.ascontiguousarray(b, dtype=np.float64)
         x = np.zeros(self.ndof) if x0 is None else np.array(x0, dtype=np.float64)
         cyc = C.c_int(0)
-        rc = lib().orc_pmg_solve(self._h, kappa, dt, tau, nu1, nu2, tol, maxcyc, _d(b), _d(x),
-                                 C.byref(cyc))
+        rc = lib().orc_pmg_solve(self._h, kappa, dt, theta, tau, nu1, nu2, tol, maxcyc, prec, coarse, solver,
+                                 1 if unlimited else 0, _d(b), _d(x), C.byref(cyc))
         return rc, x, cyc.value
 
-    def sequential(self, kappa: float, T: float, Nt: int, F: np.ndarray, tkind: int, u0: np.ndarray):
-        """Sequential implicit Euler with direct solves; returns U of shape (Nt+1, ndof)."""
+    def load_vector_fn(self, f) -> np.ndarray:
+        """int f Phi_i dOmega for a Python function f(x, y) of the physical coordinates."""
+        cb = FN2(f)
+        out = np.zeros(self.ndof)
+        lib().orc_load_vector_fn(self._h, cb, _d(out))
+        return out
+
+    def l2_error_fn(self, c: np.ndarray, u) -> float:
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        return lib().orc_l2_error_fn(self._h, _d(c), FN2(u))
+
+    def hmg_levels(self):
+        ne = np.zeros(16, dtype=np.int32)
+        nl = lib().orc_hmg_info(self._h, _i(ne))
+        return [int(v) for v in ne[:nl]]
+
+    def hmg_matrix(self, kappa, dt, k, which="A", theta=1.0):
+        """h-multigrid level-k operator ("A") or prolongation P_k ("P") of A_{h,1}, scipy CSR."""
+        import scipy.sparse as sp
+        w = 0 if which == "A" else 1
+        sh = np.zeros(3, dtype=np.int32)
+        rc = lib().orc_hmg_matrix(self._h, kappa, dt, theta, k, w, _i(sh), None, None, None)
+        if rc:
+            raise ValueError(f"hmg_matrix failed: {rc}")
+        nr, nc, nnz = (int(v) for v in sh)
+        rp = np.zeros(nr + 1, dtype=np.int32)
+        ci = np.zeros(max(nnz, 1), dtype=np.int32)
+        v = np.zeros(max(nnz, 1))
+        lib().orc_hmg_matrix(self._h, kappa, dt, theta, k, w, _i(sh), _i(rp), _i(ci), _d(v))
+        return sp.csr_matrix((v[:nnz], ci[:nnz], rp), shape=(nr, nc))
+
+    def hmg_cycles(self, kappa, dt, b, x0, ncyc, theta=1.0):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.array(x0, dtype=np.float64)
+        rc = lib().orc_hmg_cycles(self._h, kappa, dt, theta, ncyc, _d(b), _d(x))
+        if rc:
+            raise RuntimeError(f"hmg failed: {rc}")
+        return x
+
+    def gs_sweep(self, kappa, dt, b, x0, direction=1, theta=1.0):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.array(x0, dtype=np.float64)
+        lib().orc_gs_sweep(self._h, kappa, dt, theta, direction, _d(b), _d(x))
+        return x
+
+    def sequential(self, kappa: float, T: float, Nt: int, F: np.ndarray, tkind: int, u0: np.ndarray,
+                   theta: float = 1.0):
+        """Sequential theta-scheme with direct solves; returns U of shape (Nt+1, ndof)."""
         F = np.ascontiguousarray(F, dtype=np.float64)
         u0 = np.ascontiguousarray(u0, dtype=np.float64)
         U = np.zeros((Nt + 1, self.ndof))
-        rc = lib().orc_sequential(self._h, kappa, T, Nt, _d(F), tkind, _d(u0), _d(U))
+        rc = lib().orc_sequential_theta(self._h, kappa, T, Nt, _d(F), tkind, theta, _d(u0), _d(U))
         if rc:
             raise RuntimeError(f"sequential solve failed: {rc}")
         return U
 
-    def sequential_pmg(self, kappa, T, Nt, F, tkind, u0, tau=1e-12, stol=1e-12, maxcyc=100):
+    def sequential_pmg(self, kappa, T, Nt, F, tkind, u0, tau=1e-12, stol=1e-12, maxcyc=100, theta=1.0, prec=0,
+                       coarse=0, solver=0):
         F = np.ascontiguousarray(F, dtype=np.float64)
         u0 = np.ascontiguousarray(u0, dtype=np.float64)
         U = np.zeros((Nt + 1, self.ndof))
         cyc = C.c_longlong(0)
-        rc = lib().orc_sequential_pmg(self._h, kappa, T, Nt, _d(F), tkind, _d(u0), tau, stol, maxcyc,
-                                      _d(U), C.byref(cyc))
+        rc = lib().orc_sequential_pmg(self._h, kappa, T, Nt, _d(F), tkind, theta, _d(u0), tau, stol, maxcyc, prec,
+                                      coarse, solver, _d(U), C.byref(cyc))
         return rc, U, cyc.value
 
     def mgrit(self, kappa, T, Nt, F, tkind, u0, m=8, max_levels=30, coarsest_max=8, tol=1e-10,
-              max_iter=100, tau=1e-12, stol=1e-12, maxcyc=100, guess=2, ctol=0.0):
-        """MGRIT with p-multigrid spatial solves (level-0 tolerance stol, coarse levels ctol, 0 = stol).
+              max_iter=100, tau=1e-12, stol=1e-12, maxcyc=100, guess=2, ctol=0.0, theta=1.0, cycle=0, prec=0,
+              coarse=0, solver=0, threads=1):
+        """MGRIT with the spatial solver above (level-0 tolerance stol, coarse levels ctol, 0 = stol);
+        cycle 0 V, 1 W, 2 F; threads: OpenMP threads over the independent intervals of a sweep.
         Returns dict(rc, U, iters, cycles, solves, hist)."""
         F = np.ascontiguousarray(F, dtype=np.float64)
         u0 = np.ascontiguousarray(u0, dtype=np.float64)
@@ -258,8 +321,10 @@ class Problem:
         cyc = C.c_longlong(0)
         sol = C.c_longlong(0)
         hist = np.zeros(200)
-        rc = lib().orc_mgrit(self._h, kappa, T, Nt, _d(F), tkind, _d(u0), m, max_levels, coarsest_max,
-                             tol, max_iter, tau, stol, ctol, maxcyc, guess, _d(U), C.byref(it), C.byref(cyc),
-                             C.byref(sol), _d(hist))
+        iopt = np.array([m, max_levels, coarsest_max, max_iter, maxcyc, guess, cycle, prec, coarse, solver, threads],
+                        dtype=np.int32)
+        dopt = np.array([tol, tau, stol, ctol, theta], dtype=np.float64)
+        rc = lib().orc_mgrit(self._h, kappa, T, Nt, _d(F), tkind, _d(u0), _i(iopt), _d(dopt), _d(U), C.byref(it),
+                             C.byref(cyc), C.byref(sol), _d(hist))
         return dict(rc=rc, U=U, iters=it.value, cycles=cyc.value, solves=sol.value,
                     hist=hist[: it.value + 1].copy())

@@ -90,18 +90,48 @@ def test_pmg_matches_dense_solve(p, n, domain):
 
 
 def test_pmg_exact_smoother_one_cycle():
-    # with tau = 0 the ILUT factor of a banded matrix is exact as soon as the caps allow the
-    # whole band: an exact smoother solves in one V-cycle
+    # with tau = 0 and no per-row caps ILUT is the exact LU factorisation, so the first smoothing step
+    # already solves the system and one V-cycle meets the tolerance
     P = O.Problem(2, 4, 0)
     b = np.random.default_rng(9).standard_normal(P.ndof)
-    rc, x, cyc = P.pmg_solve(1.0, 0.02, b, tau=0.0, maxcyc=5)
-    # the capped factor is not exact; run the unlimited factor through the direct check instead
-    rc2, L, U = P.ilut(0.02, tau=0.0, unlimited=True)
     A = P.dense("M") + 0.02 * P.dense("K")
-    Ld = L.toarray() + np.eye(P.ndof)
-    xs = np.linalg.solve(U.toarray(), np.linalg.solve(Ld, b))
-    assert np.allclose(A @ xs, b, atol=1e-12)
-    assert rc == 0
+    for coarse in (0, 1):
+        rc, x, cyc = P.pmg_solve(1.0, 0.02, b, tau=0.0, maxcyc=5, unlimited=True, coarse=coarse)
+        assert rc == 0 and cyc == 1
+        assert np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b)
+    # with the caps of A's pattern the factor is incomplete and needs more than one cycle
+    rc, x, cyc = P.pmg_solve(1.0, 0.02, b, tau=0.0, maxcyc=50)
+    assert rc == 0 and cyc > 1
+
+
+@pytest.mark.parametrize("prec,coarse,solver", [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1)])
+def test_sequential_iterative_matches_direct(prec, coarse, solver):
+    # sequential stepping with any of the iterative spatial solvers reaches the direct solution of
+    # every step (spatial tolerance 1e-13)
+    P = O.Problem(3, 8, 1)
+    F = P.load_vector([(1, 2, 0.8), (3, 1, -0.4)])
+    u0 = P.project([(1, 1, 1.0)])
+    Us = P.sequential(0.7, 0.1, 12, F, 0, u0)
+    rc, U, cyc = P.sequential_pmg(0.7, 0.1, 12, F, 0, u0, stol=1e-13, maxcyc=2000, prec=prec, coarse=coarse,
+                                  solver=solver)
+    assert rc == 0 and cyc >= 12
+    per = np.linalg.norm(U - Us, axis=1) / np.maximum(np.linalg.norm(Us, axis=1), 1e-300)
+    assert per.max() <= 1e-11
+
+
+@pytest.mark.parametrize("p,n,domain", [(2, 8, 0), (4, 6, 1)])
+def test_pmg_fp32_refined_matches_dense(p, n, domain):
+    # FP32 V-cycles inside FP64 refinement still reach the FP64 tolerance; the FP32 V-cycle contracts
+    # about as well as the FP64 one, so the cycle counts stay close
+    P = O.Problem(p, n, domain)
+    kappa, dt = 1.3, 0.01
+    A = P.dense("M") + kappa * dt * P.dense("K")
+    b = np.random.default_rng(15).standard_normal(P.ndof)
+    rc, x, cyc = P.pmg_solve(kappa, dt, b, prec=1)
+    rc64, x64, cyc64 = P.pmg_solve(kappa, dt, b)
+    assert rc == 0 and rc64 == 0
+    assert np.linalg.norm(b - A @ x) <= 1e-12 * np.linalg.norm(b) * 1.0001
+    assert abs(cyc - cyc64) <= 2
 
 
 def test_coarse_correction_helps():
