@@ -6,14 +6,16 @@
  * to obtain a scalable solver for Isogeometric Analysis" (arXiv 2107.05337).
  *   - Problem: d_t u - kappa Lap u = f on Omega x [0,T], u(.,0) = u0, u = 0 on the boundary
  *     (Sec. 2, eq:heat), tensor-product B-splines of degree p on n x n elements of width
- *     h = 1/n with open uniform knot vectors (Sec. 2), implicit Euler (theta = 1), so every
- *     time step solves (M + kappa dt K) u^{k+1} = M u^k + dt f^{k+1} (Sec. 2, eq:los; Sec. 4).
+ *     h = 1/n with open uniform knot vectors (Sec. 2), the theta-scheme in time (implicit
+ *     Euler by default), so every time step solves (M + theta kappa dt K) u^{k+1} =
+ *     (M - (1 - theta) kappa dt K) u^k + dt f (Sec. 2, eq:los; Sec. 4).
  *   - Time parallelism: MGRIT with coarsening factor m, FCF-relaxation, injection of the
  *     C-point residual, rediscretised coarse levels dt_l = m^l dt and ideal interpolation
  *     (Sec. 3, eq:mgrit, eq:mgrit_coarse and the MGRIT recursion).
  *   - Spatial solves: p-multigrid V-cycles (Sec. 4, steps 1-5) with an ILUT smoother at
  *     degree p, direct restriction to p = 1 with the lumped-mass L2 transfers
- *     (Sec. 4, eq:prolongation, eq:PM) and an exact solve at p = 1.
+ *     (Sec. 4, eq:prolongation, eq:PM) and at p = 1 an exact solve or the paper's one
+ *     h-multigrid W-cycle; or, as the paper's comparison, Jacobi-preconditioned CG (Sec. 4).
  *
  * Conventions for every call:
  *   - Return value: PMGRIT_OK (0) or a negative pmgrit_status; no call aborts the process;
@@ -54,6 +56,12 @@ typedef enum {
 } pmgrit_status;
 
 /* One problem instance (Sec. 2, eq:heat; Sec. 5 benchmark setting).
+ * Time discretisation: the theta-scheme of Sec. 2 (eq:los), every step solving
+ *   (M + theta kappa dt K) u^{k+1} = (M - (1 - theta) kappa dt K) u^k + w_k f,
+ *   w_k = dt (theta tfac(t_{k+1}) + (1 - theta) tfac(t_k)),
+ * theta = 1 implicit (backward) Euler, 1/2 Crank-Nicolson, 0 forward Euler (then M is the
+ * operator the spatial solver inverts; stable only for small kappa dt / h^2 on every MGRIT level).
+ * Coarse MGRIT levels rediscretise with the same theta and dt_l = m^l dt.
  * domain 0: unit square (F = identity).  domain 1: quarter annulus with radii 1 and 2, first
  * parameter direction radial, second the exact rational quadratic quarter circle.
  * Source f(x, t) = tfac(t) * sum_q amp_q m(k_q, s) m(l_q, t) in parameter coordinates (s, t)
@@ -65,6 +73,8 @@ typedef struct {
   double kappa;     /* diffusion coefficient > 0 */
   double T;         /* end time > 0 */
   int32_t n_steps;  /* N_t >= 1 */
+  double theta;     /* theta-scheme parameter in [0, 1] (1 = implicit Euler; no default: a
+                     * zero-initialised struct asks for forward Euler) */
 } pmgrit_problem;
 
 /* MGRIT hierarchy and stopping rule (Sec. 3; Sec. 5).  Level l has floor(N_t / m^l)
@@ -81,6 +91,10 @@ typedef struct {
   int32_t use_graph;    /* 1: capture one iteration (coarse correction and the next relaxation,
                          * kernels only) as a HIP graph per set of trajectory buffers and stream,
                          * and replay it; 0: launch every kernel */
+  int32_t cycle;        /* cycle type of the coarse-level solves (Sec. 3): 0 V-cycle (one cycle
+                         * per level), 1 W-cycle (two cycles per level), 2 F-cycle (an F-cycle
+                         * followed by a V-cycle per level); the coarsest level is always solved
+                         * by sequential time stepping, so with two levels all three coincide */
 } pmgrit_mgrit_opts;
 
 /* Spatial solver (Sec. 4).  precision 0: FP64 V-cycle.  precision 1: V-cycle in FP32 as the
@@ -120,6 +134,15 @@ typedef struct {
                            * depend on bits 1-16; the 8-lane builds sum each triangular-solve row in
                            * another order (rounding only).  PMGRIT_E_ARG if it does not fit a
                            * group's LDS or its rows, or is combined with autotune. */
+  int32_t solver;         /* spatial solver: 0 p-multigrid V-cycles (Sec. 4); 1 conjugate gradients
+                           * preconditioned by diag(A) (the comparison solver of Sec. 4 and Sec. 5),
+                           * FP64 only (precision 0), max_vcycles then caps the CG iterations */
+  int32_t coarse;         /* p = 1 solve of the V-cycle (step 3 of Sec. 4): 0 exact (fast
+                           * diagonalisation), 1 one h-multigrid W-cycle from zero (the paper's
+                           * choice: four-colour Gauss-Seidel pre- and post-smoothing, canonical
+                           * prolongation, restriction by its transpose, Galerkin coarse operators,
+                           * meshes halved while the element count is even and above 4, the
+                           * coarsest solved exactly) */
 } pmgrit_solver_opts;
 
 typedef struct {
@@ -287,6 +310,18 @@ pmgrit_status pmgrit_group_info(const pmgrit_handle* h, int32_t inst, int64_t* o
  * leaves it as is; out4 (may be NULL) receives {total kernel ms, launches, workgroups launched,
  * V-cycles performed} accumulated since the last reset. */
 pmgrit_status pmgrit_profile(pmgrit_handle* h, int32_t enable, double* out4);
+
+/* Live per-launch timing of one launch group (same events as pmgrit_profile, same reset):
+ * out3 = {kernel ms, launches, workgroups launched} of the spatial-solve launches of group `group`
+ * (0 <= group < the group count of pmgrit_group_info) since the last reset; graph replays are not
+ * attributed to a group.  Synchronises the device.  Errors: PMGRIT_E_ARG (bad group or NULL
+ * out3), PMGRIT_E_STATE (host-only handle). */
+pmgrit_status pmgrit_group_profile(pmgrit_handle* h, int32_t group, double* out3);
+
+/* V-cycles (CG iterations with solver 1) performed for each instance since create: out receives
+ * n_instances counts.  Synchronises the device.  Errors: PMGRIT_E_ARG (NULL), PMGRIT_E_STATE
+ * (host-only handle). */
+pmgrit_status pmgrit_inst_vcycles(pmgrit_handle* h, int64_t* out);
 
 const char* pmgrit_last_error(void);
 

@@ -27,19 +27,20 @@ class PmgritError(RuntimeError):
 
 class Problem(C.Structure):
     _fields_ = [("degree_p", C.c_int32), ("n_elems", C.c_int32), ("domain", C.c_int32), ("kappa", C.c_double),
-                ("T", C.c_double), ("n_steps", C.c_int32)]
+                ("T", C.c_double), ("n_steps", C.c_int32), ("theta", C.c_double)]
 
 
 class MgritOpts(C.Structure):
     _fields_ = [("cfactor", C.c_int32), ("max_levels", C.c_int32), ("coarsest_max", C.c_int32),
-                ("tol", C.c_double), ("max_iter", C.c_int32), ("use_graph", C.c_int32)]
+                ("tol", C.c_double), ("max_iter", C.c_int32), ("use_graph", C.c_int32), ("cycle", C.c_int32)]
 
 
 class SolverOpts(C.Structure):
     _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("ilut_droptol", C.c_double), ("ilut_fill", C.c_int32),
                 ("spatial_tol", C.c_double), ("max_vcycles", C.c_int32), ("precision", C.c_int32),
                 ("guess", C.c_int32), ("trsv_block", C.c_int32), ("autotune", C.c_int32),
-                ("coarse_tol", C.c_double), ("lds_mask", C.c_int32)]
+                ("coarse_tol", C.c_double), ("lds_mask", C.c_int32), ("solver", C.c_int32),
+                ("coarse", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -94,6 +95,8 @@ def lib():
         L.pmgrit_info.argtypes = [_vp, C.POINTER(C.c_int64)]
         L.pmgrit_group_info.argtypes = [_vp, C.c_int32, C.POINTER(C.c_int64)]
         L.pmgrit_profile.argtypes = [_vp, C.c_int32, _dp]
+        L.pmgrit_group_profile.argtypes = [_vp, C.c_int32, _dp]
+        L.pmgrit_inst_vcycles.argtypes = [_vp, C.POINTER(C.c_int64)]
         L.pmgrit_net_nparams.argtypes = []
         L.pmgrit_net_nparams.restype = C.c_int64
         L.pmgrit_net_load.argtypes = [_vp, _fp, C.c_int64]
@@ -140,14 +143,14 @@ def _dptr(t):
 
 def default_solver_opts(**kw) -> SolverOpts:
     o = SolverOpts(nu1=1, nu2=1, ilut_droptol=1e-12, ilut_fill=0, spatial_tol=1e-12, max_vcycles=100, precision=0,
-                   guess=2, trsv_block=0, autotune=0, coarse_tol=0.0, lds_mask=0)
+                   guess=2, trsv_block=0, autotune=0, coarse_tol=0.0, lds_mask=0, solver=0, coarse=0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
 
 
 def default_mgrit_opts(**kw) -> MgritOpts:
-    o = MgritOpts(cfactor=8, max_levels=12, coarsest_max=8, tol=1e-10, max_iter=100, use_graph=0)
+    o = MgritOpts(cfactor=8, max_levels=12, coarsest_max=8, tol=1e-10, max_iter=100, use_graph=0, cycle=0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -208,6 +211,19 @@ class Solver:
         out = (C.c_double * 4)()
         _check(lib().pmgrit_profile(self._h, enable, out))
         return dict(ms=out[0], launches=int(out[1]), workgroups=int(out[2]), vcycles=int(out[3]))
+
+    def group_profile(self, group: int):
+        """Per-launch timing of one launch group since the last profile reset: dict(ms, launches,
+        workgroups)."""
+        out = (C.c_double * 3)()
+        _check(lib().pmgrit_group_profile(self._h, group, out))
+        return dict(ms=out[0], launches=int(out[1]), workgroups=int(out[2]))
+
+    def inst_vcycles(self):
+        """V-cycles (or CG iterations) per instance since create."""
+        out = (C.c_int64 * self.n)()
+        _check(lib().pmgrit_inst_vcycles(self._h, out))
+        return [int(v) for v in out]
 
     @staticmethod
     def _modes(modes):
@@ -364,5 +380,6 @@ class Solver:
         return x
 
 
-def problem(p: int, n: int, Nt: int, kappa: float = 1.0, T: float = 0.1, domain: int = 0) -> Problem:
-    return Problem(degree_p=p, n_elems=n, domain=domain, kappa=kappa, T=T, n_steps=Nt)
+def problem(p: int, n: int, Nt: int, kappa: float = 1.0, T: float = 0.1, domain: int = 0,
+            theta: float = 1.0) -> Problem:
+    return Problem(degree_p=p, n_elems=n, domain=domain, kappa=kappa, T=T, n_steps=Nt, theta=theta)

@@ -56,6 +56,17 @@ struct LevelHost {
   Csr A, L, U;  // A on the pattern of M
   TriSchedule SL, SU;
   std::vector<double> tl, tdinv;
+  std::vector<double> htl, htd;  // h-multigrid p = 1 solve: Thomas data of the coarsest h-level
+};
+
+// h-multigrid of the p = 1 problem: interior 1D factors Mx, Kx, Mx2, My, Ky per h-level (level 0:
+// the rediscretised p = 1 matrices; level k: Galerkin products P^T T P with the 1D canonical
+// prolongation), and the coarsest level's eigenvectors for its exact solve
+struct HmgHost {
+  std::vector<int> ne;                  // elements per direction of each h-level
+  std::vector<std::vector<Dense>> T;    // [level][5]
+  Dense Vc;
+  std::vector<double> lam;
 };
 
 struct InstHost {
@@ -67,6 +78,7 @@ struct InstHost {
   std::vector<double> mlp, ml1, F, u0, scale;
   int tkind = 0;
   CoarseFdm fdm;
+  HmgHost hmg;
   std::vector<LevelHost> lev;
 };
 
@@ -97,6 +109,7 @@ struct pmgrit_handle {
   PhiJob* h_given_jobs = nullptr;
   int given_key[3] = {-1, -1, -1};
   int fp32 = 0;
+  int ext = 0;  // kExt: the extended kernel build (theta < 1, h-multigrid p = 1 solve or CG)
   struct JobList {
     PhiJob* d = nullptr;
     int n = 0;
@@ -125,6 +138,7 @@ struct pmgrit_handle {
     int max_jobs = 0;
     double* d_ws = nullptr;
     int64_t ws_stride = 0;
+    int64_t hmg_off = 0;  // h-multigrid scratch offset in a slice
     double* d_nrm2 = nullptr;
     int* d_vcount = nullptr;
     int* d_res_begin = nullptr;  // level-0 residual workgroup ranges per group-local instance
@@ -164,6 +178,10 @@ struct pmgrit_handle {
   bool prof = false;
   std::vector<hipEvent_t> ev;
   int ev_used = 0;
+  std::vector<int> ev_group;  // launch group of each recorded event pair (-1: a graph replay)
+  std::vector<double> gprof_ms;             // per launch group: kernel ms, launches, workgroups
+  std::vector<int64_t> gprof_launches, gprof_wgs;
+  unsigned long long* d_vinst = nullptr;    // V-cycles per instance (device counters)
   double prof_ms = 0;
   int64_t vc_base = 0;  // V-cycle counter total at the last profile reset
   int64_t prof_launches = 0, prof_wgs = 0;
@@ -310,6 +328,46 @@ static pmgrit_status setup_instance(pmgrit_handle* H, InstHost& I, const pmgrit_
     I.fdm.n1 = I.n1;
     I.fdm.V = V.a;
   }
+  // h-multigrid of the p = 1 problem: halve the mesh while the element count is even and above 4
+  if (H->so.coarse == 1) {
+    HmgHost& hm = I.hmg;
+    for (int ne = n;;) {
+      hm.ne.push_back(ne);
+      if ((int)hm.ne.size() == kHmgMax || ne % 2 != 0 || ne <= 4) break;
+      ne /= 2;
+    }
+    hm.T.resize(hm.ne.size());
+    hm.T[0] = {interior(I.M1x), interior(I.K1x), interior(I.M1x2), interior(I.M1y), interior(I.K1y)};
+    for (size_t k = 1; k < hm.ne.size(); ++k) {
+      const int nf = hm.ne[k - 1] - 1, nc = hm.ne[k] - 1;
+      // canonical prolongation: coarse node J (0-based) is fine node 2J + 1; its hat is 1/2, 1, 1/2
+      // on fine nodes 2J, 2J + 1, 2J + 2
+      Dense P1(nf, nc);
+      for (int J = 0; J < nc; ++J) {
+        P1(2 * J, J) = 0.5;
+        P1(2 * J + 1, J) = 1.0;
+        P1(2 * J + 2, J) = 0.5;
+      }
+      for (const Dense& Tf : hm.T[k - 1]) {
+        Dense TP(nf, nc), C(nc, nc);
+        for (int i = 0; i < nf; ++i)
+          for (int J = 0; J < nc; ++J) {
+            double t = 0.0;
+            for (int j = std::max(0, 2 * J - 1); j <= std::min(nf - 1, 2 * J + 3); ++j) t += Tf(i, j) * P1(j, J);
+            TP(i, J) = t;
+          }
+        for (int I2 = 0; I2 < nc; ++I2)
+          for (int J = 0; J < nc; ++J) {
+            double t = 0.0;
+            for (int i = 2 * I2; i <= 2 * I2 + 2; ++i) t += P1(i, I2) * TP(i, J);
+            C(I2, J) = t;
+          }
+        hm.T[k].push_back(C);
+      }
+    }
+    const std::vector<Dense>& Tc = hm.T.back();
+    if (!gen_eig(Tc[4], Tc[3], hm.lam, hm.Vc)) return PMGRIT_E_FACTOR;
+  }
   // time levels (factored by setup_level, in parallel over instances and levels)
   const double dt0 = pr.T / pr.n_steps;
   I.nlev = H->nlev;
@@ -327,7 +385,8 @@ static pmgrit_status setup_level(const pmgrit_handle* H, InstHost& I, int l, std
   Dense G1 = interior(I.M1x), K1i = interior(I.K1x), H1 = interior(I.M1x2);
   LevelHost& Lv = I.lev[l];
   Lv.dt = dt0 * std::pow((double)H->m, l);
-  const double c = pr.kappa * Lv.dt;
+  // theta-scheme (Sec. 2, eq:los): the solves invert A_l = M + theta kappa dt_l K
+  const double c = pr.theta * pr.kappa * Lv.dt;
   Lv.A = I.M;
   for (size_t t = 0; t < Lv.A.v.size(); ++t) Lv.A.v[t] = I.M.v[t] + c * I.K.v[t];
   std::vector<int> lc(I.ndof), uc(I.ndof);
@@ -376,6 +435,33 @@ static pmgrit_status setup_level(const pmgrit_handle* H, InstHost& I, int l, std
       Lv.tl[(size_t)k * n1 + i] = li;
       Lv.tdinv[(size_t)k * n1 + i] = 1.0 / diag;
       dprev = diag;
+    }
+  }
+  if (H->so.coarse == 1) {
+    // coarsest h-level: modes of (Mx + c Kx) + c lam_k Mx2 as above
+    const std::vector<Dense>& Tc = I.hmg.T.back();
+    const int nc = Tc[0].r;
+    Lv.htl.assign((size_t)nc * nc, 0.0);
+    Lv.htd.assign((size_t)nc * nc, 0.0);
+    for (int k = 0; k < nc; ++k) {
+      double dprev = 0.0;
+      for (int i = 0; i < nc; ++i) {
+        const double lk = I.hmg.lam[k];
+        double diag = Tc[0](i, i) + c * Tc[1](i, i) + c * lk * Tc[2](i, i);
+        double li = 0.0;
+        if (i > 0) {
+          const double off = Tc[0](i, i - 1) + c * Tc[1](i, i - 1) + c * lk * Tc[2](i, i - 1);
+          li = off / dprev;
+          diag -= li * off;
+        }
+        if (!(diag > 0)) {
+          err = "coarsest h-multigrid tridiagonal not SPD";
+          return PMGRIT_E_FACTOR;
+        }
+        Lv.htl[(size_t)k * nc + i] = li;
+        Lv.htd[(size_t)k * nc + i] = 1.0 / diag;
+        dprev = diag;
+      }
     }
   }
   return PMGRIT_OK;
@@ -801,6 +887,12 @@ static pmgrit_status learned_setup(pmgrit_handle* H) {
 static pmgrit_status device_setup(pmgrit_handle* H) {
   HIPCHK(hipSetDevice(H->device));
   H->fp32 = H->so.precision == 1;
+  H->ext = 0;
+  if (H->so.coarse == 1 || H->so.solver == 1) H->ext = kExt;
+  for (const InstHost& I : H->inst)
+    if (I.prob.theta != 1.0) H->ext = kExt;
+  if (H->ext && (H->so.lds_mask & (kOcc2 | kT1024 | kW8)))
+    return fail(PMGRIT_E_ARG, "theta < 1, the h-multigrid p = 1 solve and CG run on the 512-thread build only");
   const int vt = H->fp32 ? 4 : 8;
   int dev_lds = 0;
   HIPCHK(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, H->device));
@@ -854,6 +946,7 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
         G.lds_bytes = bytes;
         G.plan = plan;
       }
+      G.mask |= H->ext;
       G.wmask = G.mask;
       G.wbytes = G.lds_bytes;
       G.wplan = G.plan;
@@ -898,14 +991,46 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
     D.F = d;
     TRY(upload_vec(H, I.scale, &d));
     D.scale = d;
+    if (H->so.coarse == 1) {
+      const HmgHost& hm = I.hmg;
+      HmgDev& hd = D.hmg;
+      hd.nh = (int)hm.ne.size();
+      int64_t words = (int64_t)(hm.ne[0] - 1) * (hm.ne[0] - 1);  // residual temporary
+      for (int k = 0; k < hd.nh; ++k) {
+        const int n1k = hm.ne[k] - 1;
+        hd.n1[k] = n1k;
+        if (k > 0) {
+          hd.off[k] = words;
+          words += 2 * (int64_t)n1k * n1k;
+        }
+        // [5][n1][3] tridiagonal rows; entries outside the matrix are zero
+        std::vector<double> band((size_t)15 * n1k, 0.0);
+        for (int mtx = 0; mtx < 5; ++mtx)
+          for (int i = 0; i < n1k; ++i)
+            for (int dd = -1; dd <= 1; ++dd)
+              if (i + dd >= 0 && i + dd < n1k) band[(size_t)3 * (mtx * n1k + i) + dd + 1] = hm.T[k][mtx](i, i + dd);
+        TRY(upload_vec(H, band, &d));
+        hd.band[k] = d;
+      }
+      hd.words = words;
+      TRY(upload_vec(H, hm.Vc.a, &d));
+      hd.Vc = d;
+    }
     for (int l = 0; l < I.nlev; ++l) {
       LevelHost& Lh = I.lev[l];
       LevelDev& Ld = D.lev[l];
       Ld.dt = Lh.dt;
-      Ld.c = I.prob.kappa * Lh.dt;
+      Ld.c = I.prob.theta * I.prob.kappa * Lh.dt;
+      Ld.cb = (1.0 - I.prob.theta) * I.prob.kappa * Lh.dt;
       Dense X1 = I.Mx;
       for (size_t t = 0; t < X1.a.size(); ++t) X1.a[t] = I.Mx.a[t] + Ld.c * I.Kx.a[t];
       TRY(upload_band(H, X1, -p, 2 * p + 1, Ld.X1));
+      // explicit part B_l = M - (1 - theta) kappa dt_l K = My (x) XB - cb Ky (x) Mx2 (theta < 1)
+      if (Ld.cb != 0.0) {
+        Dense XB = I.Mx;
+        for (size_t t = 0; t < XB.a.size(); ++t) XB.a[t] = I.Mx.a[t] - Ld.cb * I.Kx.a[t];
+        TRY(upload_band(H, XB, -p, 2 * p + 1, Ld.XB));
+      }
       // the prefetched path reads y from LDS: the y slot, or the window of the last p + 3 grid
       // lines when y is in global memory (the 1024-thread build needs the y slot)
       const bool yl = G.mask & kY, win = !yl && G.plan.off_win >= 0;
@@ -919,6 +1044,20 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
       Ld.tl = d;
       TRY(upload_vec(H, Lh.tdinv, &d));
       Ld.tdinv = d;
+      if (H->so.coarse == 1) {
+        TRY(upload_vec(H, Lh.htl, &d));
+        Ld.htl = d;
+        TRY(upload_vec(H, Lh.htd, &d));
+        Ld.htd = d;
+      }
+      if (H->so.solver == 1) {  // diag(A_l) for the Jacobi-preconditioned CG
+        std::vector<double> dg(I.ndof, 0.0);
+        for (int i = 0; i < I.ndof; ++i)
+          for (int t = Lh.A.rp[i]; t < Lh.A.rp[i + 1]; ++t)
+            if (Lh.A.ci[t] == i) dg[i] = Lh.A.v[t];
+        TRY(upload_vec(H, dg, &d));
+        Ld.dgA = d;
+      }
     }
   }
   TRY(upload_vec(H, H->h_instdev, &H->d_inst));
@@ -980,7 +1119,11 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
     TRY(upload_vec(H, G.inst, &G.d_res_inst));
     // scratch: one slice per workgroup slot; at least kGivenMax slots for pmgrit_phi
     G.max_jobs = std::max(G.max_jobs, kGivenMax);
-    G.ws_stride = (6 * (int64_t)G.nmax + 32 + 31) / 32 * 32;
+    // slice: six vectors of nmax doubles, 32 spare, then the h-multigrid scratch (coarse = 1)
+    int64_t hw = 0;
+    for (int i : G.inst) hw = std::max(hw, (int64_t)H->h_instdev[i].hmg.words);
+    G.hmg_off = 6 * (int64_t)G.nmax + 32;
+    G.ws_stride = (G.hmg_off + hw + 31) / 32 * 32;
     TRY(upload<double>(H, nullptr, (size_t)G.ws_stride * G.max_jobs, &G.d_ws));
     TRY(upload<double>(H, nullptr, (size_t)G.max_jobs, &G.d_nrm2));
     TRY(upload<int>(H, nullptr, (size_t)G.max_jobs, &G.d_vcount));
@@ -1003,6 +1146,12 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
   HIPCHK(hipHostMalloc((void**)&H->h_given_jobs, sizeof(PhiJob) * kGivenMax, 0));
   H->ev.resize(2048);
   for (auto& e : H->ev) HIPCHK(hipEventCreate(&e));
+  H->ev_group.assign(H->ev.size() / 2, -1);
+  H->gprof_ms.assign(H->groups.size(), 0.0);
+  H->gprof_launches.assign(H->groups.size(), 0);
+  H->gprof_wgs.assign(H->groups.size(), 0);
+  TRY(upload<unsigned long long>(H, nullptr, (size_t)H->ninst, &H->d_vinst));
+  HIPCHK(hipMemset(H->d_vinst, 0, sizeof(unsigned long long) * H->ninst));
   HIPCHK(hipDeviceSynchronize());
   return PMGRIT_OK;
 }
@@ -1020,6 +1169,7 @@ static PhiParams base_params(pmgrit_handle* H, const pmgrit_handle::Group& G, in
   P.gtab = H->d_gtab;
   P.nrm2 = G.d_nrm2;
   P.vcount = G.d_vcount;
+  P.vinst = H->d_vinst;
   P.status = H->d_status;
   P.ws = G.d_ws;
   P.ws_stride = G.ws_stride;
@@ -1030,6 +1180,9 @@ static PhiParams base_params(pmgrit_handle* H, const pmgrit_handle::Group& G, in
   P.nu2 = H->so.nu2;
   P.stol = H->so.spatial_tol;
   P.stolc = H->so.coarse_tol > 0 ? H->so.coarse_tol : H->so.spatial_tol;
+  P.solver = H->so.solver;
+  P.coarse = H->so.coarse;
+  P.hmg_off = G.hmg_off;
   return P;
 }
 
@@ -1040,6 +1193,8 @@ static hipError_t harvest(pmgrit_handle* H) {
     hipError_t e = hipEventElapsedTime(&ms, H->ev[2 * k], H->ev[2 * k + 1]);
     if (e != hipSuccess) return e;
     H->prof_ms += ms;
+    const int g = H->ev_group[k];
+    if (g >= 0) H->gprof_ms[g] += ms;
   }
   H->ev_used = 0;
   return hipSuccess;
@@ -1059,10 +1214,14 @@ static hipError_t phi_timed(pmgrit_handle* H, const pmgrit_handle::Group& G, con
     if ((e = harvest(H)) != hipSuccess) return e;
   }
   const int k = H->ev_used++;
+  const int gi = (int)(&G - H->groups.data());
+  H->ev_group[k] = gi;
   if ((e = hipEventRecord(H->ev[2 * k], st)) != hipSuccess) return e;
   if ((e = phi_launch(H->fp32, mask, bytes, P, plan, nblocks, st)) != hipSuccess) return e;
   H->prof_launches++;
   H->prof_wgs += nblocks;
+  H->gprof_launches[gi]++;
+  H->gprof_wgs[gi] += nblocks;
   return hipEventRecord(H->ev[2 * k + 1], st);
 }
 
@@ -1114,13 +1273,14 @@ static hipError_t net_predict(pmgrit_handle* H, int which, int s, int kbase, hip
   return hipSuccess;
 }
 
-// one recursive MGRIT cycle at level l >= 1 on A^{(l)} v = g (v zeroed by the caller)
-static hipError_t coarse_cycle(pmgrit_handle* H, int l, hipStream_t st, int64_t& phi) {
+static hipError_t level_solve(pmgrit_handle* H, int l, int kind, hipStream_t st, int64_t& phi);
+
+// One MGRIT cycle at level l >= 1 on A^{(l)} v = g from the current v (Sec. 3, the MGRIT
+// recursion): FCF-relaxation, the C-point residual injected into level l + 1, the level-(l + 1)
+// correction from zero by level_solve of the same cycle kind, the C-point update and the
+// interpolating F-relaxation.
+static hipError_t mgrit_cycle(pmgrit_handle* H, int l, int kind, hipStream_t st, int64_t& phi) {
   hipError_t e;
-  if (l == H->nlev - 1) {
-    phi += sweep_steps(H, 3, l);
-    return sweep(H, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jCoarsest; }, kModeChain, st);
-  }
   auto fl = [l](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF[l]; };
   // FCF-relaxation, then the C-point residuals injected into the next level
   if ((e = sweep(H, fl, kModeChain, st)) != hipSuccess) return e;
@@ -1131,20 +1291,34 @@ static hipError_t coarse_cycle(pmgrit_handle* H, int l, hipStream_t st, int64_t&
   if ((e = sweep(H, [l](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jRES[l]; }, kModeResidual,
                  st)) != hipSuccess)
     return e;
-  // F, C, F, residual, and the interpolating F-relaxation after the correction
-  phi += 3 * sweep_steps(H, 0, l) + sweep_steps(H, 1, l) + sweep_steps(H, 2, l);
+  // F, C, F, residual (the interpolating F-relaxation is counted where it is launched)
+  phi += 2 * sweep_steps(H, 0, l) + sweep_steps(H, 1, l) + sweep_steps(H, 2, l);
   for (int i = 0; i < H->ninst; ++i) {
     double* vc = H->h_vtab[(size_t)i * kMaxLevels + l + 1];
     if ((e = fill_launch(vc, (int64_t)(H->Nl[l + 1] + 1) * H->inst[i].ndof, 0.0, st)) != hipSuccess) return e;
   }
-  if ((e = coarse_cycle(H, l + 1, st, phi)) != hipSuccess) return e;
+  if ((e = level_solve(H, l + 1, kind, st, phi)) != hipSuccess) return e;
   for (int i = 0; i < H->ninst; ++i) {
     double* vl = H->h_vtab[(size_t)i * kMaxLevels + l];
     double* vc = H->h_vtab[(size_t)i * kMaxLevels + l + 1];
     if ((e = correct_launch(vl, vc, H->inst[i].ndof, H->m, H->Nl[l + 1], st)) != hipSuccess) return e;
   }
   // ideal interpolation = F-relaxation from the corrected C-points
+  phi += sweep_steps(H, 0, l);
   return sweep(H, [l](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jF[l]; }, kModeChain, st);
+}
+
+// Approximate solve of the level-l >= 1 problem from its current v (Sec. 3, cycle types): the
+// coarsest level by sequential time stepping; otherwise one cycle (kind 0, V), two cycles (kind 1,
+// W), or an F-cycle followed by a V-cycle (kind 2, F).
+static hipError_t level_solve(pmgrit_handle* H, int l, int kind, hipStream_t st, int64_t& phi) {
+  if (l == H->nlev - 1) {
+    phi += sweep_steps(H, 3, l);
+    return sweep(H, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jCoarsest; }, kModeChain, st);
+  }
+  hipError_t e = mgrit_cycle(H, l, kind, st, phi);
+  if (e != hipSuccess || kind == 0) return e;
+  return mgrit_cycle(H, l, kind == 1 ? 1 : 0, st, phi);
 }
 
 static pmgrit_status read_status(pmgrit_handle* H, hipStream_t st) {
@@ -1239,6 +1413,8 @@ static pmgrit_status autotune(pmgrit_handle* H) {
       for (int mk : {15, 7, 3, 1, 3 | kOcc2, 1 | kOcc2, 15 | kT1024, 7 | kT1024, 3 | kT1024, 1 | kT1024, 15 | kW8,
                      7 | kW8, 3 | kW8, 1 | kW8}) {
         if ((mk & kOcc2) && !H->fp32) continue;
+        if (H->ext && (mk & (kOcc2 | kT1024 | kW8))) continue;  // the extended build: 512 threads
+        mk |= H->ext;
         if ((mk & kW8) && G.maxrows > kRowSlots / 2) continue;
         int bytes = 0;
         const LdsPlan plan = lds_plan_mask(G.nmax, G.n1max, G.maxrows, vt, (mk & (kT1024 | kW8)) ? G.ka8 : G.ka,
@@ -1316,7 +1492,7 @@ pmgrit_status pmgrit_create(int32_t n_instances, const pmgrit_problem* probs, co
   const pmgrit_mgrit_opts& mo = *mopts;
   const pmgrit_solver_opts& so = *sopts;
   if (mo.cfactor < 2 || mo.max_levels < 1 || mo.max_levels > kMaxLevels || mo.coarsest_max < 1 || mo.max_iter < 0 ||
-      !(mo.tol >= 0) || mo.use_graph < 0 || mo.use_graph > 1)
+      !(mo.tol >= 0) || mo.use_graph < 0 || mo.use_graph > 1 || mo.cycle < 0 || mo.cycle > 2)
     return fail(PMGRIT_E_ARG, "invalid MGRIT options");
   if (so.nu1 < 1 || so.nu2 < 0 || !(so.ilut_droptol >= 0) || !(so.spatial_tol > 0) || so.max_vcycles < 1 ||
       (so.precision != 0 && so.precision != 1) || so.guess < 0 || so.guess > 3 || so.trsv_block < -1 ||
@@ -1325,12 +1501,15 @@ pmgrit_status pmgrit_create(int32_t n_instances, const pmgrit_problem* probs, co
       ((so.lds_mask & kT1024) && ((so.lds_mask & kOcc2) || !(so.lds_mask & kY))) ||
       ((so.lds_mask & kW8) && ((so.lds_mask & (kOcc2 | kT1024)) || !(so.lds_mask & kY))) ||
       ((so.lds_mask & kOcc2) && (so.precision != 1 || (so.lds_mask & 15) != ((so.lds_mask & 15) & (kY | kD)) ||
-                                 !(so.lds_mask & kY))))
+                                 !(so.lds_mask & kY))) ||
+      so.solver < 0 || so.solver > 1 || so.coarse < 0 || so.coarse > 1 ||
+      // CG runs in FP64 on the 512-thread build
+      (so.solver == 1 && (so.precision != 0 || (so.lds_mask & (kOcc2 | kT1024 | kW8)))))
     return fail(PMGRIT_E_ARG, "invalid solver options");
   for (int i = 0; i < n_instances; ++i) {
     const pmgrit_problem& p = probs[i];
     if (p.degree_p < 2 || p.degree_p > 8 || p.n_elems < 2 || p.n_elems > 1024 || (p.domain != 0 && p.domain != 1) ||
-        !(p.kappa > 0) || !(p.T > 0) || p.n_steps < 1)
+        !(p.kappa > 0) || !(p.T > 0) || p.n_steps < 1 || !(p.theta >= 0.0 && p.theta <= 1.0))
       return fail(PMGRIT_E_ARG, "invalid problem " + std::to_string(i));
     if (p.n_steps != probs[0].n_steps) return fail(PMGRIT_E_ARG, "all instances must share n_steps");
   }
@@ -1434,7 +1613,12 @@ pmgrit_status pmgrit_set_source_modes(pmgrit_handle* h, int32_t inst, int32_t n_
   I.F = modal_load(I, n_modes, k, l, amp);
   I.tkind = time_kind;
   const double dt = I.prob.T / I.prob.n_steps;
-  for (int s = 0; s <= I.prob.n_steps; ++s) I.scale[s] = dt * (time_kind == 1 ? std::exp(-s * dt) : 1.0);
+  // source weight of step s - 1 -> s, theta-weighted like the diffusion term:
+  // w = dt (theta tfac(t_s) + (1 - theta) tfac(t_{s-1})); entry 0 is dt tfac(0)
+  auto tf = [&](int s) { return time_kind == 1 ? std::exp(-s * dt) : 1.0; };
+  const double th = I.prob.theta;
+  I.scale[0] = dt * tf(0);
+  for (int s = 1; s <= I.prob.n_steps; ++s) I.scale[s] = dt * (th * tf(s) + (1.0 - th) * tf(s - 1));
   if (h->device >= 0) {
     HIPCHK(hipSetDevice(h->device));
     HIPCHK(hipMemcpy((void*)h->h_instdev[inst].F, I.F.data(), sizeof(double) * I.ndof, hipMemcpyHostToDevice));
@@ -1545,7 +1729,7 @@ static hipError_t correct_level0(pmgrit_handle* h, hipStream_t st, double* const
     double* vc = h->h_vtab[(size_t)i * kMaxLevels + 1];
     if ((e = fill_launch(vc, (int64_t)(h->Nl[1] + 1) * h->inst[i].ndof, 0.0, st)) != hipSuccess) return e;
   }
-  if ((e = coarse_cycle(h, 1, st, phi)) != hipSuccess) return e;
+  if ((e = level_solve(h, 1, h->mo.cycle, st, phi)) != hipSuccess) return e;
   for (int i = 0; i < h->ninst; ++i) {
     double* vc = h->h_vtab[(size_t)i * kMaxLevels + 1];
     if ((e = correct_launch(u_out[i], vc, h->inst[i].ndof, h->m, h->Nl[1], st)) != hipSuccess) return e;
@@ -1603,6 +1787,7 @@ static hipError_t graph_launch_timed(pmgrit_handle* h, hipStream_t st) {
     if ((e = harvest(h)) != hipSuccess) return e;
   }
   const int k = h->ev_used++;
+  h->ev_group[k] = -1;
   if ((e = hipEventRecord(h->ev[2 * k], st)) != hipSuccess) return e;
   if ((e = hipGraphLaunch(h->graph_exec, st)) != hipSuccess) return e;
   h->prof_launches += h->graph_launches;
@@ -1836,8 +2021,35 @@ pmgrit_status pmgrit_profile(pmgrit_handle* h, int32_t enable, double* out4) {
     h->prof_ms = 0;
     h->prof_launches = h->prof_wgs = 0;
     h->vc_base = vc;
+    std::fill(h->gprof_ms.begin(), h->gprof_ms.end(), 0.0);
+    std::fill(h->gprof_launches.begin(), h->gprof_launches.end(), 0);
+    std::fill(h->gprof_wgs.begin(), h->gprof_wgs.end(), 0);
   }
   if (enable >= 0) h->prof = enable == 1;
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_group_profile(pmgrit_handle* h, int32_t group, double* out3) {
+  if (!h || !out3) return fail(PMGRIT_E_ARG, "bad group-profile arguments");
+  if (h->device < 0) return fail(PMGRIT_E_STATE, "host-only handle");
+  if (group < 0 || group >= (int)h->groups.size()) return fail(PMGRIT_E_ARG, "bad launch group");
+  HIPCHK(hipSetDevice(h->device));
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(harvest(h));
+  out3[0] = h->gprof_ms[group];
+  out3[1] = (double)h->gprof_launches[group];
+  out3[2] = (double)h->gprof_wgs[group];
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_inst_vcycles(pmgrit_handle* h, int64_t* out) {
+  if (!h || !out) return fail(PMGRIT_E_ARG, "bad counter arguments");
+  if (h->device < 0) return fail(PMGRIT_E_STATE, "host-only handle");
+  HIPCHK(hipSetDevice(h->device));
+  std::vector<unsigned long long> v(h->ninst);
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(v.data(), h->d_vinst, sizeof(unsigned long long) * h->ninst, hipMemcpyDeviceToHost));
+  for (int i = 0; i < h->ninst; ++i) out[i] = (int64_t)v[i];
   return PMGRIT_OK;
 }
 

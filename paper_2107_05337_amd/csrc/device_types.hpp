@@ -63,12 +63,33 @@ struct BandDev {
 
 // one MGRIT time level of one instance: A_l = M + kappa dt_l K and its smoother / coarse data
 struct LevelDev {
-  double dt, c;        // c = kappa dt_l
+  double dt, c;        // c = theta kappa dt_l (A_l = M + c K, theta-scheme of Sec. 2)
+  double cb;           // cb = (1 - theta) kappa dt_l (B_l = M - cb K applied to the previous point)
   BandDev X1;          // first-direction factor of A_l's first term: Mx + c Kx
+  BandDev XB;          // first-direction factor of B_l's first term: Mx - cb Kx (cb != 0 only)
   TriDev L, U;         // ILUT(A_l) factors (slot tables for 4 lanes per row)
   TriDev L8, U8;       // the same factors, slot tables for 8 lanes per row
   const double* tl;    // exact p = 1 solve: Thomas multipliers per mode [n1][n1]
   const double* tdinv; //                    inverse pivots per mode [n1][n1]
+  const double* htl;   // h-multigrid p = 1 solve: Thomas data of the coarsest h-level [n1c][n1c]
+  const double* htd;
+  const double* dgA;   // diag(A_l) (ndof), for Jacobi-preconditioned CG
+};
+
+// One h-multigrid W-cycle as the p = 1 solve (Sec. 4, the paragraph after step 5).  h-level 0 is
+// the p = 1 space on n elements per direction; each further level halves the mesh while the element
+// count is even and above 4.  Operators are Galerkin products R A P with the canonical prolongation
+// P and R = P^T, which on these separable geometries keep the form
+//   A_k = My_k (x) (Mx_k + c Kx_k) + c Ky_k (x) Mx2_k
+// with 1D tridiagonal factors (c = theta kappa dt_l of the MGRIT level).
+constexpr int kHmgMax = 12;
+struct HmgDev {
+  int nh;                        // h-levels (1: the p = 1 problem is solved exactly at once)
+  int n1[kHmgMax];               // interior nodes per direction of h-level k
+  int64_t off[kHmgMax];          // scratch offset (doubles) of b_k; x_k follows it (k >= 1)
+  int64_t words;                 // scratch doubles per workgroup (residual temporary first)
+  const double* band[kHmgMax];   // [5][n1][3]: Mx, Kx, Mx2, My, Ky rows (i, i-1), (i, i), (i, i+1)
+  const double* Vc;              // coarsest level: generalized eigenvectors of (Ky, My), [iy][k]
 };
 
 // A_l = My (x) X1_l + c_l Ky (x) Mx2, M = My (x) Mx, P_1^p = Py (x) Px (second direction slow)
@@ -84,7 +105,8 @@ struct InstDev {
   const double* il1_y;
   const double* V;           // p = 1 generalized eigenvectors, [iy][k], n1 x n1
   const double* F;           // load vector (ndof)
-  const double* scale;       // level-0 source scale dt * tfac(t_k) for k = 0..N_t
+  const double* scale;       // level-0 source weight of the step k - 1 -> k at entry k (k >= 1)
+  HmgDev hmg;                // h-multigrid p = 1 solve (solver option coarse = 1)
   LevelDev lev[kMaxLevels];
 };
 
@@ -110,11 +132,15 @@ struct PhiParams {
   double* nrm2;            // residual mode: ||r||^2 per workgroup
   int* vcount;             // V-cycles per workgroup (accumulated)
   int* vlast;              // mode kModeGiven: V-cycles of this solve per workgroup (may be null)
+  unsigned long long* vinst;  // V-cycles per instance (accumulated since create)
   int* status;             // error flags (bit 0 non-finite, bit 1 V-cycle cap)
   double* ws;              // per-workgroup global scratch
   int64_t ws_stride;       // doubles per workgroup
   int mode, guess, maxcyc, nu1, nu2;
   int kshift;              // added to every job's first point (one job list serves all steps)
+  int solver;              // 0 p-multigrid, 1 Jacobi-preconditioned CG (FP64)
+  int coarse;              // p = 1 solve: 0 exact, 1 one h-multigrid W-cycle
+  int64_t hmg_off;         // offset (doubles) of the h-multigrid scratch in a workgroup's slice
   double stol;             // spatial tolerance at level 0
   double stolc;            // spatial tolerance at coarse levels
 };
@@ -139,5 +165,8 @@ constexpr int kT1024 = 32;
 // 1024-thread build's slot tables, 64 row slots); y must be in LDS and every level of the
 // group's schedules must hold at most 64 rows
 constexpr int kW8 = 64;
+// placement flag: the extended 512-thread build (theta < 1, h-multigrid p = 1 solve, CG), set by
+// the library itself whenever a handle uses one of those
+constexpr int kExt = 128;
 
 }  // namespace pmg

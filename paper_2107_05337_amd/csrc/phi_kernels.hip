@@ -689,10 +689,11 @@ __device__ __forceinline__ void coarse_transform(int n1, const G<double>* __rest
   }
 }
 
+// (G + c lam_k H) solves of one n1 x n1 grid by fast diagonalisation with eigenvectors V and the
+// Thomas data tl / tdinv of the modes: c1 in / out, c2 temporary
 template <int NT>
-__device__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, double* c2) {
-  const int n1 = I.n1;
-  const G<double>* __restrict__ V = gp(I.V);
+__device__ __forceinline__ void fdm_solve(int n1, const double* Vp, const double* tlp, const double* tdp, double* c1, double* c2) {
+  const G<double>* __restrict__ V = gp(Vp);
   coarse_transform<NT, true>(n1, V, c1, c2);  // c2[k][ix] = sum_iy V[iy][k] c1[iy][ix]
   __syncthreads();
   for (int k = threadIdx.x; k < n1; k += NT) {
@@ -700,8 +701,8 @@ __device__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, do
     // step of the recurrence
     constexpr int CH = 8;
     double* rw = c2 + k * n1;
-    const G<double>* __restrict__ tl = gp(L.tl) + k * n1;
-    const G<double>* __restrict__ td = gp(L.tdinv) + k * n1;
+    const G<double>* __restrict__ tl = gp(tlp) + k * n1;
+    const G<double>* __restrict__ td = gp(tdp) + k * n1;
     double yp = 0.0;
     for (int i0 = 0; i0 < n1; i0 += CH) {
       double a[CH], b[CH];
@@ -744,12 +745,187 @@ __device__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, do
   __syncthreads();
 }
 
+// exact p = 1 solve of A_{h,1} = M1 + c K1 (c1 in / out, c2 temporary)
+template <int NT>
+__device__ __forceinline__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, double* c2) {
+  fdm_solve<NT>(I.n1, I.V, L.tl, L.tdinv, c1, c2);
+}
+
+// ---------------------------------------------------------------------------------------
+// p = 1 solve by one h-multigrid W-cycle (Sec. 4, the paragraph after step 5): four-colour
+// Gauss-Seidel pre- and post-smoothing, residual restricted by R = P^T, two W-cycles on the next
+// level (one solve at the coarsest), prolongation of the correction by the canonical P.
+// Grids of h-level k are n1 x n1 interior nodes, first index fastest.
+// ---------------------------------------------------------------------------------------
+
+// the nine stencil coefficients of A_k at node (iy, ix): a[dy + 1][dx + 1]
+__device__ __forceinline__ void hmg_stencil(const G<double>* __restrict__ bd, int n1, int iy, int ix, double c,
+                                            double a[3][3]) {
+  const G<double>* Mx = bd + 3 * ix;
+  const G<double>* Kx = bd + 3 * (n1 + ix);
+  const G<double>* M2 = bd + 3 * (2 * n1 + ix);
+  const G<double>* My = bd + 3 * (3 * n1 + iy);
+  const G<double>* Ky = bd + 3 * (4 * n1 + iy);
+  double xa[3], xb[3], ya[3], yb[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    xa[d] = Mx[d] + c * Kx[d];
+    xb[d] = c * M2[d];
+    ya[d] = My[d];
+    yb[d] = Ky[d];
+  }
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) a[dy][dx] = ya[dy] * xa[dx] + yb[dy] * xb[dx];
+}
+
+// sum over the off-centre stencil entries of a * x around (iy, ix) (neighbours outside the grid
+// have zero coefficients: the band rows hold zeros there)
+__device__ __forceinline__ double hmg_offsum(const double a[3][3], const double* x, int n1, int iy, int ix) {
+  double s = 0.0;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      if (dy == 0 && dx == 0) continue;
+      const int jy = iy + dy, jx = ix + dx;
+      if (jy >= 0 && jy < n1 && jx >= 0 && jx < n1) s += a[dy + 1][dx + 1] * x[jy * n1 + jx];
+    }
+  return s;
+}
+
+// one Gauss-Seidel sweep in the four-colour order of the 9-point stencil (colour of node (ix, iy) is
+// (ix mod 2) + 2 (iy mod 2)): colours 0..3 (fwd) or 3..0; nodes of one colour never couple
+template <int NT>
+__device__ __forceinline__ void hmg_gs(const double* band, int n1, double c, const double* b, double* x, bool fwd) {
+  const G<double>* __restrict__ bd = gp(band);
+  for (int cc = 0; cc < 4; ++cc) {
+    const int col = fwd ? cc : 3 - cc;
+    const int ox = col & 1, oy = col >> 1;
+    const int nx = (n1 - ox + 1) >> 1, ny = (n1 - oy + 1) >> 1;
+    for (int t = threadIdx.x; t < nx * ny; t += NT) {
+      const int iy = 2 * (t / nx) + oy, ix = 2 * (t % nx) + ox;
+      double a[3][3];
+      hmg_stencil(bd, n1, iy, ix, c, a);
+      x[iy * n1 + ix] = (b[iy * n1 + ix] - hmg_offsum(a, x, n1, iy, ix)) / a[1][1];
+    }
+    __syncthreads();
+  }
+}
+
+// r = b - A_k x on h-level k, then the restriction bc = R r onto level k + 1 (coarse node J sits on
+// fine node 2J + 1, its hat has weights 1/2, 1, 1/2 on fine nodes 2J, 2J + 1, 2J + 2), xc = 0
+template <int NT>
+__device__ __forceinline__ void hmg_restrict(const double* band, int n1, double c, const double* b, const double* x, double* r,
+                             int n1c, double* bc, double* xc) {
+  const G<double>* __restrict__ bd = gp(band);
+  for (int t = threadIdx.x; t < n1 * n1; t += NT) {
+    const int iy = t / n1, ix = t - iy * n1;
+    double a[3][3];
+    hmg_stencil(bd, n1, iy, ix, c, a);
+    r[t] = b[t] - (a[1][1] * x[t] + hmg_offsum(a, x, n1, iy, ix));
+  }
+  __syncthreads();
+  const double w[3] = {0.5, 1.0, 0.5};
+  for (int t = threadIdx.x; t < n1c * n1c; t += NT) {
+    const int jy = t / n1c, jx = t - jy * n1c;
+    double s = 0.0;
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      double sx = 0.0;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) sx += w[dx] * r[(2 * jy + dy) * n1 + 2 * jx + dx];
+      s += w[dy] * sx;
+    }
+    bc[t] = s;
+    xc[t] = 0.0;
+  }
+  __syncthreads();
+}
+
+// x += P xc: fine node i (0-based) takes coarse node (i - 1) / 2 with weight 1 when i is odd, and
+// coarse nodes i / 2 - 1 and i / 2 with weights 1/2 when i is even (those that exist)
+template <int NT>
+__device__ __forceinline__ void hmg_prolong(int n1, int n1c, const double* xc, double* x) {
+  for (int t = threadIdx.x; t < n1 * n1; t += NT) {
+    const int iy = t / n1, ix = t - iy * n1;
+    int jy[2], jx[2];
+    double wy[2], wx[2];
+    if (iy & 1) { jy[0] = (iy - 1) >> 1; wy[0] = 1.0; jy[1] = 0; wy[1] = 0.0; }
+    else { jy[0] = (iy >> 1) - 1; wy[0] = 0.5; jy[1] = iy >> 1; wy[1] = 0.5; }
+    if (ix & 1) { jx[0] = (ix - 1) >> 1; wx[0] = 1.0; jx[1] = 0; wx[1] = 0.0; }
+    else { jx[0] = (ix >> 1) - 1; wx[0] = 0.5; jx[1] = ix >> 1; wx[1] = 0.5; }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const bool ok = wy[u] != 0.0 && wx[v] != 0.0 && jy[u] >= 0 && jy[u] < n1c && jx[v] >= 0 && jx[v] < n1c;
+        if (ok) s += wy[u] * wx[v] * xc[jy[u] * n1c + jx[v]];
+      }
+    x[t] += s;
+  }
+  __syncthreads();
+}
+
+// x0 = W-cycle(A_0, b0) from x0 = 0; the recursion W(k) = GS, restrict, W(k+1) twice (once when
+// k + 1 is the coarsest level, which is solved exactly), prolong, GS backwards, run as a loop over
+// the levels with one bit per level recording whether its first W(k+1) is done.  hw: scratch of
+// HmgDev::words doubles (residual temporary, then b_k, x_k of the coarser levels)
+template <int NT>
+__device__ __forceinline__ void hmg_wcycle(const InstDev& I, const LevelDev& L, const double* b0, double* x0, double* hw) {
+  const HmgDev& H = I.hmg;
+  const int last = H.nh - 1;
+  const double c = L.c;
+  double* rt = hw;
+  for (int i = threadIdx.x; i < H.n1[0] * H.n1[0]; i += NT) x0[i] = 0.0;
+  __syncthreads();
+  unsigned once = 0;  // bit k: the first W(k + 1) of level k's current activation has returned
+  int k = 0;
+  bool down = true;
+  for (;;) {
+    const int n1 = H.n1[k];
+    const double* bk = k == 0 ? b0 : hw + H.off[k];
+    double* xk = k == 0 ? x0 : hw + H.off[k] + (int64_t)n1 * n1;
+    if (down) {
+      if (k == last) {
+        for (int i = threadIdx.x; i < n1 * n1; i += NT) xk[i] = bk[i];
+        __syncthreads();
+        fdm_solve<NT>(n1, H.Vc, L.htl, L.htd, xk, rt);
+        if (k == 0) break;
+        --k;
+        down = false;
+        continue;
+      }
+      hmg_gs<NT>(H.band[k], n1, c, bk, xk, true);
+      const int n1c = H.n1[k + 1];
+      hmg_restrict<NT>(H.band[k], n1, c, bk, xk, rt, n1c, hw + H.off[k + 1], hw + H.off[k + 1] + (int64_t)n1c * n1c);
+      once &= ~(1u << k);
+      ++k;
+      continue;
+    }
+    // back on level k from one W(k + 1)
+    if (k + 1 < last && !(once & (1u << k))) {
+      once |= 1u << k;
+      ++k;
+      down = true;
+      continue;
+    }
+    const int n1c = H.n1[k + 1];
+    hmg_prolong<NT>(n1, n1c, hw + H.off[k + 1] + (int64_t)n1c * n1c, xk);
+    hmg_gs<NT>(H.band[k], n1, c, bk, xk, false);
+    if (k == 0) break;
+    --k;
+  }
+}
+
 // one p-multigrid V-cycle from the zero guess on A d = r (Sec. 4, steps 1-5, in correction
 // form: the outer FP64 loop supplies r = b - A x and adds d to x).
 // Buffers: y (nin^2 doubles, LDS first), s (>= max(nin^2 VT, n1^2 doubles)), d (nin^2 VT).
-template <typename VT, int MASK, int OCC>
+template <typename VT, int MASK, int OCC, bool EXT>
 __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, const VT* r, VT* d, VT* y, VT* s,
-                       VT* sbuf, int ka, int zidx, VT* win, int zwin) {
+                       VT* sbuf, int ka, int zidx, VT* win, int zwin, int coarse, double* hw) {
   constexpr bool YL = MASK & kY;
   constexpr int NT = Build<OCC>::NT;
   const int n = I.ndof;
@@ -776,8 +952,14 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
   __syncthreads();
   pass_y<NT, VT>(I.n1, I.nin, I.PyT, y, (VT)1, (const VT*)nullptr, (VT)0, false, I.il1_y, I.il1_x, c1);
   __syncthreads();
-  // step 3: exact p = 1 solve (FP64)
-  coarse_solve<NT>(I, L, c1, c2);
+  // step 3: p = 1 solve (FP64), exact or by one h-multigrid W-cycle
+  if (EXT && coarse == 1) {
+    hmg_wcycle<NT>(I, L, c1, c2, hw);
+    for (int i = threadIdx.x; i < I.ndof1; i += NT) c1[i] = c2[i];
+    __syncthreads();
+  } else {
+    coarse_solve<NT>(I, L, c1, c2);
+  }
   // step 4: prolongation and update d += (Mp^L)^{-1} P e1
   pass_x<NT, VT>(I.n1, I.n1, I.Px, c1, y);  // n1 rows x nin columns
   __syncthreads();
@@ -793,7 +975,55 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
   }
 }
 
-template <typename VT, int MASK, int OCC>
+// Conjugate gradients preconditioned by diag(A_l) (the comparison solver of Sec. 4 and Sec. 5),
+// FP64, textbook recursion from the iterate in x until ||r|| <= tol ||b|| (r updated by the
+// recursion) or maxcyc iterations.  r, p, q, tmp: work vectors of n_dof doubles.  Returns the
+// iterations; sets status bit 0 (non-finite) or 1 (cap).
+template <int NT, int OCC>
+__device__ __forceinline__ int pcg(const InstDev& I, const LevelDev& L, const double* b, double* x, double* r, double* p, double* q,
+                   double* tmp, double* red, double stol2, double bn2, int maxcyc, int* status) {
+  const int n = I.ndof;
+  const G<double>* __restrict__ dg = gp(L.dgA);
+  double rn2 = block_sum<NT>(apply_A<NT, double, OCC>(I, L, x, b, r, tmp), red);  // r = b - A x
+  double rho_old = 0.0;
+  int it = 0;
+  for (;; ++it) {
+    if (!(rn2 <= 1.0e300)) {
+      if (threadIdx.x == 0) atomicOr(status, 1);
+      break;
+    }
+    if (rn2 <= stol2 * bn2) break;
+    if (it >= maxcyc) {
+      if (threadIdx.x == 0) atomicOr(status, 2);
+      break;
+    }
+    double part = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) part += r[i] * (r[i] / dg[i]);
+    const double rho = block_sum<NT>(part, red);  // r . z with z = D^{-1} r
+    if (it == 0) {
+      for (int i = threadIdx.x; i < n; i += NT) p[i] = r[i] / dg[i];
+    } else {
+      const double beta = rho / rho_old;
+      for (int i = threadIdx.x; i < n; i += NT) p[i] = r[i] / dg[i] + beta * p[i];
+    }
+    __syncthreads();
+    apply_A<NT, double, OCC>(I, L, p, (const double*)nullptr, q, tmp);  // q = -A p
+    part = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) part += p[i] * q[i];
+    const double alpha = -rho / block_sum<NT>(part, red);
+    part = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) {
+      x[i] += alpha * p[i];
+      r[i] += alpha * q[i];
+      part += r[i] * r[i];
+    }
+    rn2 = block_sum<NT>(part, red);
+    rho_old = rho;
+  }
+  return it;
+}
+
+template <typename VT, int MASK, int OCC, bool EXT = false>
 __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan) {
   constexpr int NT = Build<OCC>::NT;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -841,10 +1071,21 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
     } else {
       const double* vk = Vl + (int64_t)k * n;
       const double c = job.level == 0 ? scale[k + 1] : 0.0;
-      pass_x<NT, double>(I.nin, I.nin, I.Mx, vk, yd);
-      __syncthreads();
-      pass_y<NT, double>(I.nin, I.nin, I.My, yd, 1.0, job.level == 0 ? Fv : (const double*)nullptr, c, false,
-                     nullptr, nullptr, b);
+      if (!EXT || L.cb == 0.0) {  // implicit Euler: B_l = M
+        pass_x<NT, double>(I.nin, I.nin, I.Mx, vk, yd);
+        __syncthreads();
+        pass_y<NT, double>(I.nin, I.nin, I.My, yd, 1.0, job.level == 0 ? Fv : (const double*)nullptr, c, false,
+                           nullptr, nullptr, b);
+      } else {  // theta < 1: B_l = My (x) (Mx - cb Kx) - cb Ky (x) Mx2
+        pass_x<NT, double>(I.nin, I.nin, L.XB, vk, yd);
+        __syncthreads();
+        pass_y<NT, double>(I.nin, I.nin, I.My, yd, 1.0, job.level == 0 ? Fv : (const double*)nullptr, c, false,
+                           nullptr, nullptr, b);
+        __syncthreads();
+        pass_x<NT, double>(I.nin, I.nin, I.Mx2, vk, yd);
+        __syncthreads();
+        pass_y<NT, double>(I.nin, I.nin, I.Ky, yd, -L.cb, (const double*)nullptr, 0.0, true, nullptr, nullptr, b);
+      }
       // initial iterate: 0 zero; 1 previous point; 2 current target at level 0 (the previous
       // MGRIT iterate), previous point at coarse levels (their state restarts from zero);
       // 4 at level 0: the current target (there a prediction) or the previous point, whichever
@@ -869,7 +1110,15 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
       for (int i = threadIdx.x; i < n; i += NT) x[i] = 0.0;
       __syncthreads();
     }
-    for (; bn2 != 0.0;) {
+    bool cg = false;
+    if constexpr (EXT && sizeof(VT) == 8) {
+      if (P.solver == 1) {
+        cg = true;
+        if (bn2 != 0.0)
+          cyc = pcg<NT, OCC>(I, L, b, x, (double*)r, (double*)d, (double*)s, yd, red, stol2, bn2, P.maxcyc, P.status);
+      }
+    }
+    for (; bn2 != 0.0 && !cg;) {
       // FP64 residual r = b - A x (stored in the V-cycle precision) and its norm
       part = 0.0;
       // Fused form (one first- and one second-direction pass, written straight into r) where LDS
@@ -908,7 +1157,8 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
         if (threadIdx.x == 0) atomicOr(P.status, 2);
         break;
       }
-      vcycle<VT, MASK, OCC>(I, L, P.nu1, P.nu2, r, d, y, s, sbuf, plan.ka, plan.zidx, win, plan.zwin);
+      vcycle<VT, MASK, OCC, EXT>(I, L, P.nu1, P.nu2, r, d, y, s, sbuf, plan.ka, plan.zidx, win, plan.zwin, P.coarse,
+                            ws + P.hmg_off);
       for (int i = threadIdx.x; i < n; i += NT) x[i] += (double)d[i];
       __syncthreads();
       ++cyc;
@@ -936,6 +1186,7 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
   if (threadIdx.x == 0) {
     P.vcount[blockIdx.x] += total;
     if (P.vlast) P.vlast[blockIdx.x] = total;
+    if (total) atomicAdd(P.vinst + job.inst, (unsigned long long)total);
   }
 }
 
@@ -1008,10 +1259,27 @@ __global__ void __launch_bounds__(512) phi_kernel_w8(PhiParams P, LdsPlan plan) 
   phi_body<VT, MASK, 4>(P, plan);
 }
 
+// the extended build (512 threads, 4 lanes per row): also theta < 1 right-hand sides, the
+// h-multigrid p = 1 solve and (FP64) the CG spatial solver; kept apart so that the other builds'
+// register allocation carries none of that code
+template <typename VT, int MASK>
+__global__ void __launch_bounds__(512) phi_kernel_x(PhiParams P, LdsPlan plan) {
+  phi_body<VT, MASK, 1, true>(P, plan);
+}
+
 using PhiFn = void (*)(PhiParams, LdsPlan);
 
 template <typename VT>
 static PhiFn pick(int mask) {
+  if (mask & kExt) {
+    switch (mask & 15) {
+      case 15: return phi_kernel_x<VT, 15>;
+      case 7: return phi_kernel_x<VT, 7>;
+      case 3: return phi_kernel_x<VT, 3>;
+      case 1: return phi_kernel_x<VT, 1>;
+      default: return phi_kernel_x<VT, 0>;
+    }
+  }
   if (mask & kT1024) {
     switch (mask & 15) {
       case 15: return phi_kernel_t<VT, 15>;

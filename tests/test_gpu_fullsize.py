@@ -1,11 +1,23 @@
-"""GPU parity at full size: the mixed-precision configuration (p = 4, h = 2^-7, N_t = 2048) and the
-heterogeneous batch of 16 instances (h 2^-5 .. 2^-8, p 2 .. 5, square and quarter annulus).
+"""GPU parity at full size against the oracle's sequential implicit Euler with direct solves (what
+converged MGRIT reproduces, Sec. 3, eq:mgrit):
 
-Where the oracle's sequential implicit Euler is affordable the whole trajectory is compared (1e-10
-relative in the discrete L2 norm over all time points); otherwise its first steps are compared one
-by one and, at sampled later steps, the step equations (M + kappa dt K) u_{k+1} = M u_k + dt F are
-checked with the oracle's own matrices (a property that holds at any size)."""
+- the mixed-precision configuration (p = 4, h = 2^-7, N_t = 2048), FP64 and FP32-refined: the whole
+  trajectory, computed by the oracle in a host thread while the GPU solves;
+- the heterogeneous batch of 16 instances (h 2^-5 .. 2^-8, p 2 .. 5, square and quarter annulus): every
+  instance with h >= 2^-6 over its whole trajectory, and every instance with h = 2^-7 or 2^-8 at ten
+  sampled steps including the last, against oracle values stored by
+  tests/golden/make_hetero16_samples.py (values at 512 seeded dofs, four seeded projections and the
+  norm of each sampled step);
+- the learned-warm-start configuration (p = 3, h = 2^-6, N_t = 4096): sequential stepping with the
+  learned guess, whole trajectory.
+
+Bars: 1e-10 relative in the discrete L2 norm over the stacked trajectory and the largest per-step
+relative error over all steps (or over the sampled steps) below 1e-10.  MGRIT runs to a 1e-12 relative
+residual here: a 1e-10 residual bounds the error only up to the norm of the inverse of the all-at-once
+operator, so the per-step bar needs the tighter stop."""
+import os
 import sys
+import threading
 
 import numpy as np
 import pytest
@@ -21,6 +33,7 @@ from paper_2107_05337_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 EPS = 1e-10
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hetero16_oracle_samples.npz")
 
 
 def say(*a):
@@ -39,85 +52,157 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def solver(insts, m, precision, tol, ctol=0.0):
+def per_step_max(U, Us):
+    num = np.linalg.norm(U[1:] - Us[1:], axis=1)
+    den = np.linalg.norm(Us[1:], axis=1)
+    return float(np.max(num / np.maximum(den, 1e-300)))
+
+
+def solver(insts, m, precision, tol, ctol=0.0, guess=2, stol=1e-12):
     probs = [pm.problem(d["p"], d["n"], d["Nt"], d["kappa"], d["T"], d["domain"]) for d in insts]
     S = pm.Solver(probs, pm.default_mgrit_opts(cfactor=m, max_levels=12, coarsest_max=8, tol=tol),
-                  pm.default_solver_opts(precision=precision, coarse_tol=ctol), device=0)
+                  pm.default_solver_opts(precision=precision, coarse_tol=ctol, guess=guess, spatial_tol=stol),
+                  device=0)
     for i, d in enumerate(insts):
         S.set_source(i, d["src"], d["tkind"])
     return S
 
 
-def oracle_steps(d, nsteps):
+def oracle_full(d):
     P = O.Problem(d["p"], d["n"], d["domain"])
-    T = d["T"] * nsteps / d["Nt"]
-    return P.sequential(d["kappa"], T, nsteps, P.load_vector(d["src"]), d["tkind"], np.zeros(P.ndof))
+    return P.sequential(d["kappa"], d["T"], d["Nt"], P.load_vector(d["src"]), d["tkind"], np.zeros(P.ndof))
 
 
-def step_residuals(d, U, ks):
-    """max over sampled k of ||(M + kappa dt K) u_{k+1} - M u_k - dt F|| / ||M u_k + dt F|| (oracle matrices)"""
-    P = O.Problem(d["p"], d["n"], d["domain"])
-    M, K = P.scipy("M"), P.scipy("K")
-    F = P.load_vector(d["src"])
-    dt = d["T"] / d["Nt"]
-    worst = 0.0
-    for k in ks:
-        b = M @ U[k] + dt * F
-        r = (M + d["kappa"] * dt * K) @ U[k + 1] - b
-        worst = max(worst, float(np.linalg.norm(r) / np.linalg.norm(b)))
-    return worst
+class Background:
+    """runs f() on a host thread (the oracle's C code releases the GIL) while the GPU works"""
+
+    def __init__(self, f):
+        self.out, self.err = None, None
+
+        def run():
+            try:
+                self.out = f()
+            except BaseException as e:  # pragma: no cover
+                self.err = e
+        self.t = threading.Thread(target=run, daemon=True)
+        self.t.start()
+
+    def get(self):
+        self.t.join()
+        if self.err is not None:
+            raise self.err
+        return self.out
 
 
+@pytest.mark.timeout(900)
 def test_mixed_precision_full_size(torch):
     cfg = W.config("heat-p4-h128-Nt2048")
     d = cfg["instances"][0]
-    say("case full size p=4 h=2^-7 N_t=2048: FP64 and FP32-refined MGRIT")
+    say("case full size p=4 h=2^-7 N_t=2048: FP64 and FP32-refined MGRIT, whole trajectory vs the oracle")
+    ref = Background(lambda: oracle_full(d))
     res = {}
     for prec in (0, 1):
-        S = solver(cfg["instances"], cfg["m"], prec, 1e-10)
+        S = solver(cfg["instances"], cfg["m"], prec, 1e-12)
         (U,), st = S.solve_mgrit()
         res[prec] = U.cpu().numpy()
         say(f"  precision {prec}: iters {st['mgrit_iters']} V-cycles {st['vcycles']} t={st['t_solve_s']:.2f}s "
             f"levels {S.dims(0)[2]}")
         S.close()
-    # FP32 V-cycle inside FP64 refinement: per-step error against the FP64 run
-    per_step = np.linalg.norm(res[1] - res[0], axis=1) / np.maximum(np.linalg.norm(res[0], axis=1), 1e-300)
-    say(f"  FP32-refined vs FP64: max per-step rel {per_step[1:].max():.2e}, total {rel(res[1], res[0]):.2e}")
-    assert per_step[1:].max() <= 1e-10
-    ns = 128
-    Us = oracle_steps(d, ns)
+    ps = per_step_max(res[1], res[0])
+    say(f"  FP32-refined vs FP64: max per-step rel {ps:.2e}, total {rel(res[1], res[0]):.2e}")
+    assert ps <= 1e-10
+    Us = ref.get()
     for prec in (0, 1):
-        e = rel(res[prec][: ns + 1], Us)
-        say(f"  precision {prec}: first {ns} steps vs oracle {e:.2e}")
-        assert e <= EPS
-        w = step_residuals(d, res[prec], [ns, 511, 1024, 1536, 2047])
-        say(f"  precision {prec}: sampled step residuals {w:.2e}")
-        assert w <= 1e-8
+        e, ek = rel(res[prec], Us), per_step_max(res[prec], Us)
+        say(f"  precision {prec} vs oracle: eps {e:.2e}, max per-step {ek:.2e}")
+        assert e <= EPS and ek <= EPS
 
 
+@pytest.mark.timeout(900)
 def test_heterogeneous_batch_full_size(torch):
+    from concurrent.futures import ThreadPoolExecutor
+
     cfg = W.config("hetero-16")
     insts = cfg["instances"]
-    say("case full size heterogeneous batch of 16 (FP32-refined, coarse tolerance 1e-6)")
-    S = solver(insts, cfg["m"], 1, 1e-11, 1e-6)
+    small = [i for i, d in enumerate(insts) if d["n"] <= 64]
+    large = [i for i, d in enumerate(insts) if d["n"] >= 128]
+    say("case full size heterogeneous batch of 16 (FP32-refined, spatial tolerance 1e-13, coarse levels 1e-6, "
+        "MGRIT to 1e-12)")
+    pool = ThreadPoolExecutor(max_workers=8)
+    futs = {i: pool.submit(oracle_full, insts[i]) for i in small}
+    # level-0 spatial solves to 1e-13: at p = 5 the conditioning of M + kappa dt K (about 1e3) turns a
+    # 1e-12 relative residual into per-step errors just above 1e-10 at the first, smallest steps
+    S = solver(insts, cfg["m"], 1, 1e-12, 1e-6, stol=1e-13)
     U, st = S.solve_mgrit()
     say(f"  iters {st['mgrit_iters']} V-cycles {st['vcycles']} t={st['t_solve_s']:.1f}s "
         f"groups {S.group_info(0)['groups']}")
     U = [u.cpu().numpy() for u in U]
     S.close()
-    checked_full = checked_res = 0
-    done128 = False
-    for i, d in enumerate(insts):
-        if d["n"] <= 64 or (d["n"] == 128 and not done128):
-            done128 = done128 or d["n"] == 128
-            e = rel(U[i], oracle_steps(d, d["Nt"]))
-            say(f"  instance {i} p={d['p']} n={d['n']} domain={d['domain']}: eps={e:.2e}")
-            assert e <= EPS
-            checked_full += 1
-    largest = max(range(len(insts)), key=lambda i: (insts[i]["n"], insts[i]["p"]))
-    d = insts[largest]
-    w = step_residuals(d, U[largest], [0, 100, 513, 1023])
-    say(f"  instance {largest} p={d['p']} n={d['n']}: sampled step residuals {w:.2e}")
-    assert w <= 1e-8
-    checked_res += 1
-    assert checked_full >= 9
+    for i in small:
+        Us = futs[i].result()
+        e, ek = rel(U[i], Us), per_step_max(U[i], Us)
+        d = insts[i]
+        say(f"  instance {i} p={d['p']} n={d['n']} domain={d['domain']}: eps={e:.2e} per-step max={ek:.2e}")
+        assert e <= EPS and ek <= EPS
+    pool.shutdown()
+    g = np.load(GOLDEN)
+    steps = [int(k) for k in g["steps"]]
+    assert sorted(int(i) for i in g["instances"]) == large and steps[-1] == insts[0]["Nt"]
+    for i in large:
+        d = insts[i]
+        nd = U[i].shape[1]
+        idx = np.sort(np.random.default_rng(1000 + i).choice(nd, 512, replace=False))
+        rng = np.random.default_rng(2000 + i)
+        Wq = np.stack([rng.standard_normal(nd) for _ in range(4)])
+        nrm, vals, proj = g[f"norm_{i}"], g[f"vals_{i}"], g[f"proj_{i}"]
+        worst = 0.0
+        for r, k in enumerate(steps):
+            u = U[i][k]
+            worst = max(worst,
+                        np.abs(u[idx] - vals[r]).max() / nrm[r],
+                        np.abs(Wq @ u - proj[r]).max() / (nrm[r] * np.sqrt(nd)),
+                        abs(np.linalg.norm(u) - nrm[r]) / nrm[r])
+        say(f"  instance {i} p={d['p']} n={d['n']} domain={d['domain']}: sampled steps {steps[0]}..{steps[-1]} "
+            f"worst rel {worst:.2e}")
+        assert worst <= EPS
+
+
+@pytest.mark.timeout(900)
+def test_learned_warm_start_full_size(torch):
+    """p = 3, h = 2^-6, N_t = 4096, a network trained (on the GPU, by the library's kernels) on sequential
+    trajectories of 8 other sources, then sequential stepping of an unseen source with the learned guess:
+    the trajectory equals the oracle's; V-cycles against the previous-step guess are reported."""
+    cfg = W.config("heat-p3-h64-Nt4096")
+    d = cfg["instances"][0]
+    say("case learned warm start p=3 h=2^-6 N_t=4096 (sequential)")
+    src = W.random_modes(1000)
+    dd = dict(d, src=src)
+    ref = Background(lambda: oracle_full(dd))
+    mk = lambda n, g: pm.Solver([pm.problem(d["p"], d["n"], d["Nt"], d["kappa"], d["T"], d["domain"])] * n,
+                                pm.default_mgrit_opts(), pm.default_solver_opts(guess=g), device=0)
+    T = mk(8, 1)
+    for i in range(8):
+        T.set_source(i, W.random_modes(i), 0)
+    Utr, _ = T.solve_sequential()
+    T.net_load(W.net_init(0).astype(np.float32))
+    tr = T.net_train(Utr, epochs=2, batch=128, lr=2e-3, seed=1)
+    theta = T.net_save()
+    T.close()
+    del Utr
+    say(f"  trained: loss {tr['loss_first']:.3e} -> {tr['loss_last']:.3e} in {tr['seconds']:.1f}s")
+    out = {}
+    for g in (1, 3):
+        S = mk(1, g)
+        S.set_source(0, src, 0)
+        if g == 3:
+            S.net_load(theta)
+        (U,), st = S.solve_sequential()
+        out[g] = (U.cpu().numpy(), st)
+        S.close()
+    Us = ref.get()
+    for g, name in ((1, "previous"), (3, "learned")):
+        U, st = out[g]
+        e, ek = rel(U, Us), per_step_max(U, Us)
+        say(f"  {name}: eps={e:.2e} per-step max={ek:.2e} V-cycles/solve {st['vcycles'] / st['phi_calls']:.3f} "
+            f"t={st['t_solve_s']:.2f}s")
+        assert e <= EPS and ek <= EPS

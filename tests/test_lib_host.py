@@ -203,3 +203,42 @@ def test_schedule_levels_capped_at_row_slots():
         assert free_rows > 128  # the uncapped schedule would overflow the row slots
         assert s["max_rows"] <= 128
         assert s["levels"] == _block_levels(T, lower, bs, 128)[0] > free_levels
+
+
+@pytest.mark.parametrize("kw", [dict(theta=-0.1), dict(theta=1.5), dict(theta=float("nan"))])
+def test_rejects_invalid_theta(kw):
+    with pytest.raises(pm.PmgritError) as e:
+        prob = pm.problem(2, 6, 16, **kw)
+        pm.Solver([prob], pm.default_mgrit_opts(), pm.default_solver_opts(), device=-1)
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("so,mo", [(dict(solver=2), {}), (dict(coarse=2), {}), (dict(solver=1, precision=1), {}),
+                                   (dict(solver=-1), {}), ({}, dict(cycle=3)), ({}, dict(cycle=-1))])
+def test_rejects_invalid_solver_variants(so, mo):
+    with pytest.raises(pm.PmgritError) as e:
+        pm.Solver([pm.problem(2, 6, 16)], pm.default_mgrit_opts(**mo), pm.default_solver_opts(**so), device=-1)
+    assert e.value.code == -1
+
+
+def test_factor_failure_reported():
+    """A non-finite operator (kappa dt K overflows) makes the factorisation fail: PMGRIT_E_FACTOR with a
+    message, no handle."""
+    with pytest.raises(pm.PmgritError) as e:
+        host_solver(2, 6, kappa=1e308, T=1.0, Nt=1)
+    assert e.value.code == -4
+    assert "SPD" in str(e.value) or "pivot" in str(e.value) or "factor" in str(e.value).lower()
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.5])
+def test_theta_level_operator_matches_oracle(theta):
+    """A_l = M + theta kappa dt_l K is the operator the library factors (theta-scheme, Sec. 2)"""
+    p, n, Nt, T, kappa = 3, 6, 32, 0.1, 0.7
+    prob = pm.problem(p, n, Nt, kappa=kappa, T=T, theta=theta)
+    S = pm.Solver([prob], pm.default_mgrit_opts(cfactor=4, coarsest_max=2), pm.default_solver_opts(), device=-1)
+    P = O.Problem(p, n, 0)
+    for level in (0, 1):
+        dt = T / Nt * 4 ** level
+        A = S.host_matrix("A", level=level)
+        Ao = P.scipy("M") + theta * kappa * dt * P.scipy("K")
+        assert abs(A - Ao).max() <= 1e-13 * abs(Ao).max()
