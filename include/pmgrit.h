@@ -203,6 +203,19 @@ pmgrit_status pmgrit_solve_sequential(pmgrit_handle* h, void* hip_stream, double
 pmgrit_status pmgrit_phi(pmgrit_handle* h, int32_t inst, int32_t level, int32_t nrhs, const double* b_dev,
                          double* x_dev, int32_t* vcycles_dev, void* hip_stream);
 
+/* pmgrit_phi for callers that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same solves, but the kernels' per-workgroup scratch (work
+ * vectors that do not fit in LDS, the h-multigrid levels) lives in a fixed device array of 2^23
+ * doubles (64 MiB) per GPU instead of the handle's buffer, and the call itself allocates nothing.
+ * The array is part of the library's code object, held by each GPU the library runs on until the
+ * process ends; its address is resolved once per device in pmgrit_create.  Every call on one GPU
+ * shares that GPU's array (no contents are carried between calls): calls that overlap in time on one
+ * GPU, from any handle or stream, race and must be ordered by the caller.  Errors: as pmgrit_phi,
+ * and PMGRIT_E_ARG when nrhs times the instance's per-workgroup scratch (6 n_dof,max + 32 doubles
+ * plus the h-multigrid levels with solver option coarse = 1) exceeds 2^23 doubles. */
+pmgrit_status pmgrit_phi_noalloc(pmgrit_handle* h, int32_t inst, int32_t level, int32_t nrhs, const double* b_dev,
+                                 double* x_dev, int32_t* vcycles_dev, void* hip_stream);
+
 /* Host-side inspection of the assembled data of instance inst (valid for every handle).
  * which: 0 M, 1 K, 2 A_level = M + kappa dt_level K, 3 L of ILUT(A_level) (strict lower),
  * 4 U of ILUT(A_level) (upper incl. diagonal), 5 P_1^p (interior, n_dof x n_dof1),

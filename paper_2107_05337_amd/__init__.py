@@ -88,6 +88,7 @@ def lib():
         L.pmgrit_solve_mgrit.argtypes = [_vp, _vp, C.POINTER(_vp), C.POINTER(Stats)]
         L.pmgrit_solve_sequential.argtypes = [_vp, _vp, C.POINTER(_vp), C.POINTER(Stats)]
         L.pmgrit_phi.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
+        L.pmgrit_phi_noalloc.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp]
         L.pmgrit_host_matrix.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int32, _ip, _ip, _ip, _dp]
         L.pmgrit_host_vectors.argtypes = [_vp, C.c_int32, _dp, _dp, _dp, _dp]
         L.pmgrit_host_schedule.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int32, _ip]
@@ -281,6 +282,14 @@ class Solver:
         nrhs = b.shape[0]
         vc = _dptr(vcycles) if vcycles is not None else _vp()
         _check(lib().pmgrit_phi(self._h, inst, level, nrhs, _dptr(b), _dptr(x), vc, _vp(_stream_ptr(stream))))
+        return x
+
+    def phi_noalloc(self, inst: int, level: int, b, x, vcycles=None, stream=None):
+        """pmgrit_phi with the kernels' scratch in the library's fixed device array (no allocation)"""
+        nrhs = b.shape[0]
+        vc = _dptr(vcycles) if vcycles is not None else _vp()
+        _check(lib().pmgrit_phi_noalloc(self._h, inst, level, nrhs, _dptr(b), _dptr(x), vc,
+                                        _vp(_stream_ptr(stream))))
         return x
 
     # ---- learned warm start ----

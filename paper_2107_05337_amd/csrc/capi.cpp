@@ -28,6 +28,8 @@ hipError_t copy_launch(double* dst, const double* src, int64_t n, hipStream_t st
 hipError_t correct_launch(double* Vl, const double* Vc, int ndof, int m, int ncoarse, hipStream_t st);
 hipError_t norm_reduce_launch(const double* nrm2, const int* begin, const int* id, double* out, int ninst,
                               hipStream_t st);
+hipError_t scratch_setup(int device);
+double* scratch_ptr(int device);
 }  // namespace pmg
 
 using namespace pmg;
@@ -886,6 +888,8 @@ static pmgrit_status learned_setup(pmgrit_handle* H) {
 
 static pmgrit_status device_setup(pmgrit_handle* H) {
   HIPCHK(hipSetDevice(H->device));
+  // address of this device's fixed scratch (the allocation-free entry point), resolved once per device
+  HIPCHK(scratch_setup(H->device));
   H->fp32 = H->so.precision == 1;
   H->ext = 0;
   if (H->so.coarse == 1 || H->so.solver == 1) H->ext = kExt;
@@ -1938,6 +1942,40 @@ pmgrit_status pmgrit_phi(pmgrit_handle* h, int32_t inst, int32_t level, int32_t 
   P.bgiven = b_dev;
   P.xgiven = x_dev;
   P.vlast = vcycles_dev;
+  HIPCHK(phi_timed(h, G, P, nrhs, st));
+  return PMGRIT_OK;
+}
+
+pmgrit_status pmgrit_phi_noalloc(pmgrit_handle* h, int32_t inst, int32_t level, int32_t nrhs, const double* b_dev,
+                                 double* x_dev, int32_t* vcycles_dev, void* hip_stream) {
+  if (!h || inst < 0 || inst >= h->ninst || level < 0 || level >= h->nlev || nrhs < 0 || nrhs > kGivenMax ||
+      (nrhs > 0 && (!b_dev || !x_dev)))
+    return fail(PMGRIT_E_ARG, "bad pmgrit_phi_noalloc arguments");
+  if (h->device < 0) return fail(PMGRIT_E_STATE, "host-only handle");
+  if (nrhs == 0) return PMGRIT_OK;
+  pmgrit_handle::Group& G = h->groups[h->inst_group[inst]];
+  if ((int64_t)nrhs * G.ws_stride > kScratchDoubles)
+    return fail(PMGRIT_E_ARG, "pmgrit_phi_noalloc: nrhs * " + std::to_string(G.ws_stride) +
+                                  " scratch doubles exceed the fixed scratch of " + std::to_string(kScratchDoubles));
+  double* ws = scratch_ptr(h->device);
+  if (!ws) return fail(PMGRIT_E_STATE, "fixed scratch not set up on this device");
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIPCHK(hipSetDevice(h->device));
+  if (h->given_key[0] != inst || h->given_key[1] != level || h->given_key[2] < nrhs) {
+    // the pinned staging buffer may still feed an earlier copy: wait before rewriting it
+    HIPCHK(hipDeviceSynchronize());
+    for (int j = 0; j < nrhs; ++j) h->h_given_jobs[j] = PhiJob{inst, level, 0, 1, 0, 0};
+    HIPCHK(hipMemcpyAsync(G.d_given_jobs, h->h_given_jobs, sizeof(PhiJob) * nrhs, hipMemcpyHostToDevice, st));
+    h->given_key[0] = inst;
+    h->given_key[1] = level;
+    h->given_key[2] = nrhs;
+  }
+  PhiParams P = base_params(h, G, kModeGiven, G.d_given_jobs);
+  P.vtab = nullptr;
+  P.bgiven = b_dev;
+  P.xgiven = x_dev;
+  P.vlast = vcycles_dev;
+  P.ws = ws;  // the per-workgroup slices live in the fixed scratch instead of the handle's buffer
   HIPCHK(phi_timed(h, G, P, nrhs, st));
   return PMGRIT_OK;
 }

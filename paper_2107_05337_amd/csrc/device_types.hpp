@@ -169,4 +169,8 @@ constexpr int kW8 = 64;
 // the library itself whenever a handle uses one of those
 constexpr int kExt = 128;
 
+// fixed device scratch of the allocation-free spatial-solve entry point: 64 MiB per device
+constexpr int64_t kScratchDoubles = (int64_t)1 << 23;
+constexpr int kMaxDevices = 64;
+
 }  // namespace pmg

@@ -17,6 +17,8 @@
 // grid lines they couple to from an LDS window.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device_types.hpp"
 
 namespace pmg {
@@ -1307,6 +1309,36 @@ static PhiFn pick(int mask) {
     case 1: return phi_kernel<VT, 1>;
     default: return phi_kernel<VT, 0>;
   }
+}
+
+// ------------------------------------------------------------------------------------------
+// fixed device scratch of the allocation-free spatial-solve entry point
+// ------------------------------------------------------------------------------------------
+// kScratchDoubles doubles (64 MiB) per device, held until the process ends.  Host code must not use
+// the array's name as a device address: scratch_setup resolves the address once per device (with that
+// device current) and keeps it.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+static double* g_scratch_ptr[kMaxDevices] = {};
+static int g_scratch_ready[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// call with `device` current
+hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ready[device]) return hipSuccess;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = (double*)ptr;
+  g_scratch_ready[device] = 1;
+  return hipSuccess;
+}
+
+double* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices && g_scratch_ready[device]) ? g_scratch_ptr[device] : nullptr;
 }
 
 // allow the kernel of a placement the device's whole per-workgroup LDS: several plans (wide and
