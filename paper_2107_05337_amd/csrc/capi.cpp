@@ -406,8 +406,12 @@ static pmgrit_status setup_level(const pmgrit_handle* H, InstHost& I, int l, std
   if (bs == 0) {
     // 64 consecutive rows per block, whatever the grid lines: four full wavefronts of the
     // 512-thread build per level (a 65-row line would leave a fifth wavefront nearly empty, and
-    // the level waits for it), and lines shorter than 64 rows share blocks, so fewer levels
-    bs = std::min(I.ndof, kWaveBlock);
+    // the level waits for it), and lines shorter than 64 rows share blocks, so fewer levels.
+    // Instances whose FP64-sized triangular-solve vector cannot be in LDS run in window mode, where
+    // each level waits on table loads from HBM: blocks of 128 rows halve the dependent levels.
+    // (FP32 V-cycles only: the FP64 window solve keeps 64-row blocks, see kWinDense)
+    const bool window = (int64_t)I.ndof * 8 + 16 + 512 + kSbufWords * 8 > (int64_t)kLdsBytes;
+    bs = std::min(I.ndof, window && H->so.precision == 1 ? kWinBlock : kWaveBlock);
   } else if (bs == -1) {
     // one grid line per block, split evenly when a line exceeds the prefetched path's 72 rows
     const int parts = (I.Nin + kDenseMax - 1) / kDenseMax;
@@ -624,7 +628,8 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
   int maxq = 0;  // the dense start column travels in 16 bits of the slot metadata
   for (int c : S.dq0) maxq = std::max(maxq, c);
   const size_t aslots = ((size_t)S.nlev * std::max(1, S.max_rows) + 1) * (size_t)RW;
-  T.fast = (zidx >= 0 && S.max_rows <= kRowSlots && maxo <= RW && maxo <= kOffMax && maxd <= kDenseMax &&
+  T.fast = (zidx >= 0 && S.max_rows <= kRowSlots && maxo <= RW && maxo <= kOffMax &&
+            maxd <= ((winW > 0 && H->fp32) ? kDenseWin : kDenseMax) &&
             maxq < 65536 && S.dval.size() + 1 < (size_t)INT32_MAX && aslots * sizeof(double) < (size_t)kBufBytes &&
             (winW == 0 || window_fits(S, winW, winN)))
                ? 1
@@ -753,18 +758,33 @@ static pmgrit_status upload_band(pmgrit_handle* H, const Dense& full, int lo, in
 // A placement without y in LDS gets the triangular solves' LDS window (winw words, 0: none)
 // when it fits.
 static void add_window(LdsPlan& plan, int& off, int mask, int vt, int winw, int dev_lds) {
-  if ((mask & kY) || winw <= 0) return;
-  const int sz = (winw * vt + 15) / 16 * 16;
-  if (off + sz > dev_lds) return;
-  plan.off_win = off;
-  plan.zwin = winw - 1;
-  off += sz;
+  if (!(mask & kY) && winw > 0) {
+    const int sz = (winw * vt + 15) / 16 * 16;
+    if (off + sz <= dev_lds) {
+      plan.off_win = off;
+      plan.zwin = winw - 1;
+      off += sz;
+    }
+  }
+  // staging area of the p = 1 transforms: over the window (never in use at the same time), extended
+  // to its size, or after the work vectors when it fits; none otherwise
+  const int st = kStageDoubles * 8;
+  if (plan.off_win >= 0) {
+    const int end = std::max(off, plan.off_win + st);
+    if (end <= dev_lds) {
+      plan.off_stage = plan.off_win;
+      off = end;
+    }
+  } else if (off + st <= dev_lds) {
+    plan.off_stage = off;
+    off += st;
+  }
 }
 
 static void lds_plan(int nmax, int n1max, int maxrows, int vt, int ka, int dev_lds, int winw, int& mask, int& bytes,
                      LdsPlan& out) {
   auto al = [](int b) { return (b + 15) / 16 * 16; };
-  const int base = 512 + al(std::max(maxrows, 256) * vt);  // block-sum scratch, sbuf (256 words)
+  const int base = 512 + al(std::max(maxrows, kSbufWords) * vt);  // block-sum scratch, sbuf
   const int sz_y = al(nmax * 8 + 16), sz_d = al(nmax * vt), sz_s = al(std::max(nmax * vt, n1max * 8)),
             sz_x = al(nmax * 8);
   const int masks[5] = {15, 7, 3, 1, 0};
@@ -790,13 +810,14 @@ static void lds_plan(int nmax, int n1max, int maxrows, int vt, int ka, int dev_l
 static LdsPlan lds_plan_mask(int nmax, int n1max, int maxrows, int vt, int ka, int dev_lds, int winw, int mask,
                              int& bytes) {
   auto al = [](int b) { return (b + 15) / 16 * 16; };
-  int off = 512 + al(std::max(maxrows, 256) * vt);
+  int off = 512 + al(std::max(maxrows, kSbufWords) * vt);
   LdsPlan plan{-1, -1, -1, -1, 512, nmax, nmax * 8 / vt, ka, -1, 0};
   if (mask & kY) { plan.off_y = off; off += al(nmax * 8 + 16); }
   if (mask & kD) { plan.off_d = off; off += al(nmax * vt); }
   if (mask & kS) { plan.off_s = off; off += al(std::max(nmax * vt, n1max * 8)); }
   if (mask & kX) { plan.off_x = off; off += al(nmax * 8); }
-  add_window(plan, off, mask, vt, winw, dev_lds);
+  // the two-workgroups-per-CU build must keep its plan within half the CU's LDS
+  add_window(plan, off, mask, vt, winw, (mask & kOcc2) ? dev_lds / 2 : dev_lds);
   bytes = off <= dev_lds ? off : 0;
   return plan;
 }
@@ -1386,7 +1407,10 @@ static pmgrit_status autotune(pmgrit_handle* H) {
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   for (pmgrit_handle::Group& G : H->groups) {
-    if (!(G.mask & kY)) continue;  // placements without y in LDS use the general solve
+    // groups whose triangular-solve vector is not in LDS (window mode): only the wide (level-0)
+    // placement is tuned, between one and two workgroups per CU (FP32)
+    const bool window = !(G.mask & kY);
+    if (window && (!H->fp32 || H->ext || G.plan.off_win < 0)) continue;
     const int inst = G.inst[0];
     const int nd = H->inst[inst].ndof;
     // two probes: as wide as a level-0 sweep (the wide placement) and as narrow as a level-1
@@ -1415,7 +1439,8 @@ static pmgrit_status autotune(pmgrit_handle* H) {
     auto probe = [&](int n, int& best_mask, int& best_bytes, LdsPlan& best_plan, float& best_ms) -> hipError_t {
       best_ms = 1e30f;
       for (int mk : {15, 7, 3, 1, 3 | kOcc2, 1 | kOcc2, 15 | kT1024, 7 | kT1024, 3 | kT1024, 1 | kT1024, 15 | kW8,
-                     7 | kW8, 3 | kW8, 1 | kW8}) {
+                     7 | kW8, 3 | kW8, 1 | kW8, 0, kOcc2}) {
+        if (window != ((mk & 15) == 0)) continue;  // window groups: the placements without y in LDS
         if ((mk & kOcc2) && !H->fp32) continue;
         if (H->ext && (mk & (kOcc2 | kT1024 | kW8))) continue;  // the extended build: 512 threads
         mk |= H->ext;
@@ -1462,7 +1487,7 @@ static pmgrit_status autotune(pmgrit_handle* H) {
     int nm = G.mask, nb = G.lds_bytes, wm = G.mask, wb = G.lds_bytes;
     LdsPlan np = G.plan, wp = G.plan;
     float nms = 0.f, wms = 0.f;
-    HIPCHK(probe(nnarrow, nm, nb, np, nms));
+    if (!window) HIPCHK(probe(nnarrow, nm, nb, np, nms));
     if (nwide > H->ncu) {
       HIPCHK(probe(nwide, wm, wb, wp, wms));
     } else {

@@ -14,6 +14,17 @@ constexpr int kOffMax = 64;
 // bytes (every table of that path is smaller); an offset at or past it reads zeros
 constexpr unsigned kBufBytes = 0x7ffff000u;
 constexpr int kDenseMax = 72;
+// window mode (work vectors in global memory, latency-bound levels): blocks of up to 128 rows, so
+// dense rows of up to 128 entries and half as many dependent levels
+constexpr int kDenseWin = 128;
+constexpr int kWinBlock = 128;
+// words of the triangular solves' LDS block-sum buffer (a level's rows plus the dense rows' reach)
+constexpr int kSbufWords = 320;
+// LDS staging area of the exact p = 1 solve's dense transforms (doubles)
+constexpr int kStageDoubles = 2048;
+constexpr int kStageMinN1 = 128;  // used from this many p = 1 nodes per direction up
+// LDS per workgroup of gfx950 (160 KiB)
+constexpr int kLdsBytes = 160 * 1024;
 // default row-block size of the triangular solves
 constexpr int kWaveBlock = 64;
 
@@ -152,6 +163,7 @@ struct LdsPlan {
   int ka;         // off-block entries per lane of the prefetched triangular solves (2, 4, 8, 16)
   int off_win;    // y not in LDS: LDS window of the triangular solves (-1: none)
   int zwin;       // index (in V-cycle words) of the window's always-zero word
+  int off_stage = -1;  // staging area of the p = 1 transforms, kStageDoubles (-1: none)
 };
 
 enum : int { kY = 1, kD = 2, kS = 4, kX = 8 };

@@ -362,12 +362,20 @@ __device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t rs, int off, uns
 // stored relative to the zero word zidx, so a zeroed unit is a zero coefficient on that word.
 // With WIN, y is the LDS window of the last winW grid lines (columns in the tables are window
 // slots) and each solved row also goes to yg, the solution in global memory.
-template <typename VT, bool IN_GLOBAL, int KA, int OCC, bool WIN>
+// widest dense row of the window mode: 128-row blocks in FP32; FP64 keeps kDenseMax (its two dense
+// buffers would not fit the register budget at 128)
+template <typename VT>
+constexpr int kWinDense = sizeof(VT) == 4 ? kDenseWin : kDenseMax;
+
+// DM: the widest dense row (kDenseMax, or kDenseWin for the FP32 window mode's larger blocks).
+template <typename VT, bool IN_GLOBAL, int KA, int OCC, bool WIN, int DM = kDenseMax>
 __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, const VT* in_g, L3<VT>* y,
                                        L3<VT>* sbuf, VT* yg) {
   constexpr int TG = Build<OCC>::TG, RW = KA * TG, V = 16 / (int)sizeof(VT);
-  // dense values per lane: a row holds up to kDenseMax values after up to V - 1 of alignment
-  constexpr int BCM = (kDenseMax + V - 1 + TG * V - 1) / (TG * V) * V;
+  // dense values per lane: a row holds up to DM values after up to V - 1 of alignment
+  constexpr int BCM = (DM + V - 1 + TG * V - 1) / (TG * V) * V;
+  // phase B reads sbuf from the row's aligned first dense column over TG * BCM values
+  static_assert(kRowSlots - 1 + TG * BCM <= kSbufWords, "sbuf too small for the dense rows");
   constexpr int WA = KA < V ? KA : V;  // off-block entries per unit
   constexpr int NU = KA / WA;          // off-block units per lane
   constexpr int ND = BCM / V;          // dense units per lane
@@ -613,18 +621,18 @@ __device__ __forceinline__ void trsv(const TriDev& T, int ka, int zidx, const VT
       trsv_fast<VT, IN_GLOBAL, 12, OCC, false>(&T, zidx, in, yl, sl, nullptr);
     else
       trsv_fast<VT, IN_GLOBAL, 16, OCC, false>(&T, zidx, in, yl, sl, nullptr);
-  } else if (!YLDS && IN_GLOBAL && OCC == 1 && win && T.fast && T.winW > 0) {
+  } else if (!YLDS && IN_GLOBAL && (OCC == 1 || OCC == 2) && win && T.fast && T.winW > 0) {
     L3<VT>* wl = (L3<VT>*)win;
     if (ka <= 2)
-      trsv_fast<VT, true, 2, 1, true>(&T, zwin, in, wl, sl, y);
+      trsv_fast<VT, true, 2, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
     else if (ka <= 4)
-      trsv_fast<VT, true, 4, 1, true>(&T, zwin, in, wl, sl, y);
+      trsv_fast<VT, true, 4, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
     else if (ka <= 8)
-      trsv_fast<VT, true, 8, 1, true>(&T, zwin, in, wl, sl, y);
+      trsv_fast<VT, true, 8, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
     else if (ka <= 12)
-      trsv_fast<VT, true, 12, 1, true>(&T, zwin, in, wl, sl, y);
+      trsv_fast<VT, true, 12, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
     else
-      trsv_fast<VT, true, 16, 1, true>(&T, zwin, in, wl, sl, y);
+      trsv_fast<VT, true, 16, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
   } else {
     trsv_general<VT, Build<OCC>::NT>(T, in, y, sbuf);
   }
@@ -691,66 +699,135 @@ __device__ __forceinline__ void coarse_transform(int n1, const G<double>* __rest
   }
 }
 
+// The same transform with both operands staged through LDS (`stage`: kStageDoubles): output tiles
+// of 128 x TX (TX = 64 with 512 threads, 128 with 1024), a 4 x 4 block per thread, the contraction in
+// chunks of 8 whose W and input slices every thread reads from LDS.  The global loads of a chunk are
+// shared by the whole tile, instead of each thread streaming its own W rows and input columns.
+template <int NT, bool TRANS>
+__device__ __forceinline__ void coarse_transform_lds(int n1, const G<double>* __restrict__ V, const double* in,
+                                                     double* out, double* stage) {
+  constexpr int TA = 128, TX = NT / 8, KC = 8;
+  static_assert((TA / 4) * (TX / 4) == NT && KC * (TA + TX) <= kStageDoubles, "tile shape");
+  L3<double>* ws = (L3<double>*)stage;  // [KC][TA]
+  L3<double>* vs = ws + KC * TA;        // [KC][TX]
+  const int ta = threadIdx.x / (TX / 4), tx = threadIdx.x % (TX / 4);
+  for (int a0 = 0; a0 < n1; a0 += TA)
+    for (int x0 = 0; x0 < n1; x0 += TX) {
+      double acc[4][4] = {};
+      for (int k0 = 0; k0 < n1; k0 += KC) {
+        __syncthreads();  // the previous chunk has been consumed
+        for (int e = threadIdx.x; e < KC * TA; e += NT) {
+          // consecutive threads take consecutive columns of V in both layouts
+          const int kk = TRANS ? e / TA : e % KC, aa = TRANS ? e % TA : e / KC;
+          const int b = k0 + kk, a = a0 + aa;
+          ws[kk * TA + aa] = (b < n1 && a < n1) ? (TRANS ? V[b * n1 + a] : V[a * n1 + b]) : 0.0;
+        }
+        for (int e = threadIdx.x; e < KC * TX; e += NT) {
+          const int kk = e / TX, xx = e % TX;
+          const int b = k0 + kk, x = x0 + xx;
+          vs[e] = (b < n1 && x < n1) ? in[b * n1 + x] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int kk = 0; kk < KC; ++kk) {
+          double w[4], v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            w[u] = ws[kk * TA + ta * 4 + u];
+            v[u] = vs[kk * TX + tx * 4 + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[u][q] += w[u] * v[q];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int a = a0 + ta * 4 + u, x = x0 + tx * 4 + q;
+          if (a < n1 && x < n1) out[a * n1 + x] = acc[u][q];
+        }
+    }
+}
+
 // (G + c lam_k H) solves of one n1 x n1 grid by fast diagonalisation with eigenvectors V and the
-// Thomas data tl / tdinv of the modes: c1 in / out, c2 temporary
+// Thomas data tl / tdinv of the modes: c1 in / out, c2 temporary; stage: an LDS staging area of
+// kStageDoubles for the transforms (null: the transforms read their operands directly)
 template <int NT>
-__device__ __forceinline__ void fdm_solve(int n1, const double* Vp, const double* tlp, const double* tdp, double* c1, double* c2) {
+__device__ __forceinline__ void fdm_solve(int n1, const double* Vp, const double* tlp, const double* tdp, double* c1,
+                                          double* c2, double* stage = nullptr) {
   const G<double>* __restrict__ V = gp(Vp);
-  coarse_transform<NT, true>(n1, V, c1, c2);  // c2[k][ix] = sum_iy V[iy][k] c1[iy][ix]
+  if (stage)
+    coarse_transform_lds<NT, true>(n1, V, c1, c2, stage);
+  else
+    coarse_transform<NT, true>(n1, V, c1, c2);  // c2[k][ix] = sum_iy V[iy][k] c1[iy][ix]
   __syncthreads();
   for (int k = threadIdx.x; k < n1; k += NT) {
-    // the coefficients are loaded 8 at a time so their latency is paid once per chunk, not per
-    // step of the recurrence
+    // the coefficients and the row values are loaded 8 at a time, ahead of the recurrence, so their
+    // latency is paid once per chunk, not per step; results are stored after the chunk
     constexpr int CH = 8;
     double* rw = c2 + k * n1;
     const G<double>* __restrict__ tl = gp(tlp) + k * n1;
     const G<double>* __restrict__ td = gp(tdp) + k * n1;
     double yp = 0.0;
     for (int i0 = 0; i0 < n1; i0 += CH) {
-      double a[CH], b[CH];
+      double a[CH], b[CH], v[CH];
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         const int i = i0 + u < n1 ? i0 + u : n1 - 1;
         a[u] = tl[i];
         b[u] = td[i];
+        v[u] = rw[i];
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         const int i = i0 + u;
-        if (i < n1) {
-          const double yv = rw[i] - (i > 0 ? a[u] * yp : 0.0);
-          rw[i] = yv * b[u];
-          yp = yv;
-        }
+        const double yv = v[u] - (i > 0 ? a[u] * yp : 0.0);
+        v[u] = yv * b[u];
+        yp = i < n1 ? yv : yp;
       }
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (i0 + u < n1) rw[i0 + u] = v[u];
     }
     double xn = 0.0;
     for (int i1 = n1 - 1; i1 >= 0; i1 -= CH) {
-      double a[CH];
+      double a[CH], v[CH];
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         const int i = i1 - u + 1;  // multiplier l_{i+1} for row i = i1 - u
         a[u] = (i >= 1 && i < n1) ? tl[i] : 0.0;
+        v[u] = rw[i1 - u >= 0 ? i1 - u : 0];
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         const int i = i1 - u;
         if (i >= 0) {
-          xn = (i == n1 - 1) ? rw[i] : rw[i] - a[u] * xn;
-          rw[i] = xn;
+          xn = (i == n1 - 1) ? v[u] : v[u] - a[u] * xn;
+          v[u] = xn;
         }
       }
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (i1 - u >= 0) rw[i1 - u] = v[u];
     }
   }
   __syncthreads();
-  coarse_transform<NT, false>(n1, V, c2, c1);  // c1[iy][ix] = sum_k V[iy][k] c2[k][ix]
+  if (stage)
+    coarse_transform_lds<NT, false>(n1, V, c2, c1, stage);
+  else
+    coarse_transform<NT, false>(n1, V, c2, c1);  // c1[iy][ix] = sum_k V[iy][k] c2[k][ix]
   __syncthreads();
 }
 
-// exact p = 1 solve of A_{h,1} = M1 + c K1 (c1 in / out, c2 temporary)
+// exact p = 1 solve of A_{h,1} = M1 + c K1 (c1 in / out, c2 temporary); the LDS-staged transforms
+// only from n1 = 128 up (at smaller sizes the direct ones have fewer dependent steps)
 template <int NT>
-__device__ __forceinline__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, double* c2) {
-  fdm_solve<NT>(I.n1, I.V, L.tl, L.tdinv, c1, c2);
+__device__ __forceinline__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, double* c2,
+                                             double* stage) {
+  fdm_solve<NT>(I.n1, I.V, L.tl, L.tdinv, c1, c2, I.n1 >= kStageMinN1 ? stage : nullptr);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -927,7 +1004,7 @@ __device__ __forceinline__ void hmg_wcycle(const InstDev& I, const LevelDev& L, 
 // Buffers: y (nin^2 doubles, LDS first), s (>= max(nin^2 VT, n1^2 doubles)), d (nin^2 VT).
 template <typename VT, int MASK, int OCC, bool EXT>
 __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, const VT* r, VT* d, VT* y, VT* s,
-                       VT* sbuf, int ka, int zidx, VT* win, int zwin, int coarse, double* hw) {
+                       VT* sbuf, int ka, int zidx, VT* win, int zwin, int coarse, double* hw, double* stage) {
   constexpr bool YL = MASK & kY;
   constexpr int NT = Build<OCC>::NT;
   const int n = I.ndof;
@@ -960,7 +1037,10 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
     for (int i = threadIdx.x; i < I.ndof1; i += NT) c1[i] = c2[i];
     __syncthreads();
   } else {
-    coarse_solve<NT>(I, L, c1, c2);
+    coarse_solve<NT>(I, L, c1, c2, stage);
+    // the staging area may overlap the triangular solves' window: restore its zero word, which the
+    // solves read for padding entries (FP64 data left there can read as a NaN in FP32)
+    if (stage && I.n1 >= kStageMinN1 && win && threadIdx.x == 0) win[zwin] = (VT)0;
   }
   // step 4: prolongation and update d += (Mp^L)^{-1} P e1
   pass_x<NT, VT>(I.n1, I.n1, I.Px, c1, y);  // n1 rows x nin columns
@@ -1046,12 +1126,15 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
   VT* s = (MASK & kS) ? (VT*)(smem + plan.off_s) : (VT*)(ws + 5 * nm);
 
   // the triangular solves read padding columns from the LDS word y[zidx], which stays zero, and
-  // read sbuf (256 words) beyond a level's rows with zero coefficients: make it finite once
+  // read sbuf (kSbufWords words) beyond a level's rows with zero coefficients: make it finite once
   if ((MASK & kY) && threadIdx.x == 0) y[plan.zidx] = (VT)0;
   // window of the triangular solves when y is in global memory; its zero word likewise
   VT* win = (!(MASK & kY) && plan.off_win >= 0) ? (VT*)(smem + plan.off_win) : nullptr;
+  // LDS staging area of the p = 1 transforms (it may share the window's bytes: the two are never in
+  // use at once); the builds limited to 128 registers keep the direct transforms
+  double* stage = (plan.off_stage >= 0 && (OCC == 1 || OCC == 4)) ? (double*)(smem + plan.off_stage) : nullptr;
   if (win && threadIdx.x == 0) win[plan.zwin] = (VT)0;
-  for (int i = threadIdx.x; i < 256; i += NT) sbuf[i] = (VT)0;
+  for (int i = threadIdx.x; i < kSbufWords; i += NT) sbuf[i] = (VT)0;
   double* Vl = P.vtab ? P.vtab[job.inst * kMaxLevels + job.level] : nullptr;
   const double* Gl = (P.gtab && job.level > 0) ? P.gtab[job.inst * kMaxLevels + job.level] : nullptr;
   const double* Fv = I.F;
@@ -1160,7 +1243,7 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
         break;
       }
       vcycle<VT, MASK, OCC, EXT>(I, L, P.nu1, P.nu2, r, d, y, s, sbuf, plan.ka, plan.zidx, win, plan.zwin, P.coarse,
-                            ws + P.hmg_off);
+                                 ws + P.hmg_off, stage);
       for (int i = threadIdx.x; i < n; i += NT) x[i] += (double)d[i];
       __syncthreads();
       ++cyc;
@@ -1301,6 +1384,7 @@ static PhiFn pick(int mask) {
   if constexpr (sizeof(VT) == 4) {
     if (mask == (3 | kOcc2)) return phi_kernel_o2<VT, 3>;
     if (mask == (1 | kOcc2)) return phi_kernel_o2<VT, 1>;
+    if (mask == kOcc2) return phi_kernel_o2<VT, 0>;  // window mode, two workgroups per CU
   }
   switch (mask & 15) {
     case 15: return phi_kernel<VT, 15>;

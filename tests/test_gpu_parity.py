@@ -326,3 +326,23 @@ def test_w8_build_needs_64_row_levels(torch):
     gi = S.group_info(0)
     assert not ((gi["lds_mask"] | gi["lds_mask_wide"]) & 64)
     S.close()
+
+
+def test_window_mode_128_row_blocks(torch):
+    """FP32 triangular solves in window mode (y in global memory, mask 2) with 128-row blocks (the block
+    size instances too large for LDS get): the trajectory reaches the oracle's, as with the default
+    placement and 64-row blocks."""
+    cfg = W.small("x", 3, 130, 16)
+    d = cfg["instances"][0]
+    say("case window mode, 128-row blocks, p=3 n=130 N_t=16 FP32")
+    P = O.Problem(d["p"], d["n"], d["domain"])
+    Us = P.sequential(d["kappa"], d["T"], d["Nt"], P.load_vector(d["src"]), d["tkind"], P.project(d["init"]))
+    for blk, mask in ((128, 2), (0, 0)):
+        S = make_solver(cfg, precision=1, trsv_block=blk, lds_mask=mask, tol=1e-12, stol=1e-13)
+        sch = S.host_schedule()
+        (U,), st = S.solve_mgrit()
+        e = rel(U.cpu().numpy(), Us)
+        say(f"  block {sch['block_size']} levels {sch['levels']} mask {S.group_info(0)['lds_mask']}: "
+            f"iters {st['mgrit_iters']} V-cycles {st['vcycles']} eps {e:.2e}")
+        assert e <= 1e-10
+        S.close()

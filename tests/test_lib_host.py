@@ -242,3 +242,13 @@ def test_theta_level_operator_matches_oracle(theta):
         A = S.host_matrix("A", level=level)
         Ao = P.scipy("M") + theta * kappa * dt * P.scipy("K")
         assert abs(A - Ao).max() <= 1e-13 * abs(Ao).max()
+
+
+@pytest.mark.parametrize("precision,bs", [(1, 128), (0, 64)])
+def test_window_instances_get_128_row_blocks(precision, bs):
+    """An instance whose FP64-sized triangular-solve vector cannot be in LDS (h = 2^-8) is scheduled in
+    blocks of 128 rows for the FP32 V-cycle (window mode), 64 otherwise"""
+    S = host_solver(2, 256, Nt=8, trsv_block=0, precision=precision)
+    s = S.host_schedule()
+    assert s["block_size"] == bs and s["max_rows"] <= 128
+    assert host_solver(3, 32, Nt=8, trsv_block=0, precision=precision).host_schedule()["block_size"] == 64
