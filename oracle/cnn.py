@@ -4,12 +4,15 @@ The network is not part of the paper; it predicts an initial iterate for the spa
 implicit Euler steps (Sec. 2, eq:los) from the current coefficients and the source.  Definition:
 
 * grid: the (n+p) x (n+p) tensor-product coefficient grid (the Dirichlet ring of coefficients is zero);
-* input planes (pack): u_k / s, (dt F_i / m_i) / s with m the row-sum-lumped mass (the explicit source
-  increment in coefficient space), and the constant ln(kappa dt n^2) / 4; s = rms(u_k) + rms(dt F / m)
-  over the interior (s = 1 when both vanish);
+* input planes (pack): u_k / s_u; e / s_e with e = (w F - kappa dt K u_k) / m, the residual b - A u_k of the
+  step's equation at the previous point divided by the row-sum-lumped mass m (the explicit increment in
+  coefficient space; w is the step's source weight); and the constant ln(kappa dt n^2) / 4; s_u = rms(u_k),
+  s_e = rms(e) over the interior (1 when zero);
 * four 3x3 cross-correlations with zero padding, channels 3 -> 32 -> 32 -> 32 -> 1, bias, ReLU after the
-  first three; the output y is the scaled increment: guess = u_k + s y on the interior;
-* training target t = (u_{k+1} - u_k) / s, loss = mean over samples and interior points of (y - t)^2.
+  first three; the output y is the increment in units of s_e: guess = u_k + s_e y on the interior;
+* training target t = (u_{k+1} - u_k) / s_e, loss = mean over samples and interior points of (y - t)^2.
+  The increment of an implicit step is A^{-1} applied to that residual, a smoothed version of e, so the
+  target is of order one whatever the state's size.
 
 Parameters are one flat float array, layer by layer: weights [cout][cin][3][3] then bias [cout].
 
@@ -132,26 +135,29 @@ def loss_and_grad(theta, x, t, round_bf16=False):
     return loss, flatten(grads)
 
 
-def pack(u, F, mlp, dt, kappa, n, p, u_next=None):
+def pack(u, F, mlp, K, w, kdt, n, p, u_next=None):
     """Input planes of one sample and (optionally) its training target.
 
-    u, F, mlp, u_next: interior vectors of length (n+p-2)^2, x fastest.  Returns (x (3, G, G), s, t (G, G))."""
+    u, F, mlp, u_next: interior vectors of length (n+p-2)^2, x fastest; K: the interior stiffness matrix
+    (dense or scipy sparse); w: the step's source weight; kdt: kappa dt.  Returns (x (3, G, G), s_e,
+    t (G, G))."""
     G = n + p
     nin = G - 2
-    c1 = dt * np.asarray(F, np.float64) / np.asarray(mlp, np.float64)
     u = np.asarray(u, np.float64)
-    s = np.sqrt(np.mean(u * u)) + np.sqrt(np.mean(c1 * c1))
-    if s == 0.0:
-        s = 1.0
+    e = (w * np.asarray(F, np.float64) - kdt * (K @ u)) / np.asarray(mlp, np.float64)
+    s_u = np.sqrt(np.mean(u * u))
+    s_e = np.sqrt(np.mean(e * e))
+    s_u = s_u if s_u != 0.0 else 1.0
+    s_e = s_e if s_e != 0.0 else 1.0
     x = np.zeros((3, G, G))
-    x[0, 1:-1, 1:-1] = (u / s).reshape(nin, nin)
-    x[1, 1:-1, 1:-1] = (c1 / s).reshape(nin, nin)
-    x[2, :, :] = np.log(kappa * dt * n * n) / 4.0
+    x[0, 1:-1, 1:-1] = (u / s_u).reshape(nin, nin)
+    x[1, 1:-1, 1:-1] = (e / s_e).reshape(nin, nin)
+    x[2, :, :] = np.log(kdt * n * n) / 4.0
     t = None
     if u_next is not None:
         t = np.zeros((G, G))
-        t[1:-1, 1:-1] = ((np.asarray(u_next, np.float64) - u) / s).reshape(nin, nin)
-    return x, s, t
+        t[1:-1, 1:-1] = ((np.asarray(u_next, np.float64) - u) / s_e).reshape(nin, nin)
+    return x, s_e, t
 
 
 def unpack(y, u, s):

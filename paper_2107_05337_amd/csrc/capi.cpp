@@ -847,10 +847,18 @@ static pmgrit_status learned_setup(pmgrit_handle* H) {
     S.F = D.F;
     S.ilx = D.ilp_x;
     S.ily = D.ilp_y;
+    S.scale = D.scale;
+    S.My = D.My.f64;
+    S.Ky = D.Ky.f64;
+    S.Kx = D.Kx.f64;
+    S.Mx2 = D.Mx2.f64;
     S.dt = I.lev[0].dt;
-    S.lnc = std::log(I.prob.kappa * S.dt * (double)I.prob.n_elems * (double)I.prob.n_elems) / 4.0;
+    S.kdt = I.prob.kappa * S.dt;
+    S.lnc = std::log(S.kdt * (double)I.prob.n_elems * (double)I.prob.n_elems) / 4.0;
     S.nin = I.Nin;
     S.G = I.Nin + 2;
+    S.p = I.p;
+    S.bw = 2 * I.p + 1;
   }
   TRY(upload<NetSrc>(H, nullptr, (size_t)H->ninst, &H->d_netsrc));
   TRY(upload<NetSrc>(H, nullptr, 1, &H->d_src_tmp));
@@ -998,6 +1006,7 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
     TRY(upload_band(H, I.Mx2, -p, 2 * p + 1, D.Mx2));
     TRY(upload_band(H, I.My, -p, 2 * p + 1, D.My));
     TRY(upload_band(H, I.Ky, -p, 2 * p + 1, D.Ky));
+    TRY(upload_band(H, I.Kx, -p, 2 * p + 1, D.Kx));
     TRY(upload_band(H, I.Px, -p, p + 2, D.Px));
     TRY(upload_band(H, I.Py, -p, p + 2, D.Py));
     TRY(upload_band(H, transpose_dense(I.Px), -1, p + 2, D.PxT));
@@ -2230,7 +2239,9 @@ pmgrit_status pmgrit_net_pack(pmgrit_handle* h, int32_t inst, int32_t level, int
   S.U = U_dev;
   S.Uout = nullptr;
   S.dt = I.lev[level].dt;
-  S.lnc = std::log(I.prob.kappa * S.dt * (double)I.prob.n_elems * (double)I.prob.n_elems) / 4.0;
+  S.kdt = I.prob.kappa * S.dt;
+  S.lnc = std::log(S.kdt * (double)I.prob.n_elems * (double)I.prob.n_elems) / 4.0;
+  if (level > 0) S.scale = nullptr;  // coarse levels: the step's own dt weights the source
   std::vector<NetPick> pk(nb);
   for (int j = 0; j < nb; ++j) pk[j] = {0, k_host[j]};
   HIPCHK(hipStreamSynchronize(st));

@@ -108,6 +108,7 @@ struct InstDev {
   int ndof, n1, ndof1, nlev;
   int nt, nin, p, pad0;
   BandDev Mx, Mx2, My, Ky;   // nin x (2p+1)
+  BandDev Kx;                // nin x (2p+1): stiffness factor (the learned guess's explicit increment)
   BandDev Px, Py;            // nin x (p+2): prolongation directions
   BandDev PxT, PyT;          // n1 x (p+2): restriction directions
   const double* ilp_x;       // 1 / lumped degree-p mass per direction (nin)

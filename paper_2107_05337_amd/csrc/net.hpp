@@ -28,9 +28,13 @@ struct NetSrc {
   const double* F;     // load vector (nin^2)
   const double* ilx;   // 1 / lumped mass per direction (nin): 1 / m_i = ilx[ix] ily[iy]
   const double* ily;
+  const double* scale; // source weight of step k -> k + 1 at entry k + 1 (null: dt)
+  // K = My (x) Kx + Ky (x) Mx2 as interior band arrays, bw = 2p + 1 entries per row
+  const double *My, *Ky, *Kx, *Mx2;
   double dt;           // step of the solves the guesses are for
+  double kdt;          // kappa dt
   double lnc;          // ln(kappa dt n^2) / 4
-  int nin, G, pad0, pad1;
+  int nin, G, p, bw;
 };
 
 struct NetPick {
@@ -89,6 +93,8 @@ class NetState {
   uint16_t *a0_ = nullptr, *a1_ = nullptr, *a2_ = nullptr, *ga_ = nullptr, *gb_ = nullptr;
   float *x_ = nullptr, *t_ = nullptr, *y_ = nullptr, *dy_ = nullptr;
   double* s_ = nullptr;
+  double* ebuf_ = nullptr;    // explicit increments of the packed samples (FP64, nb x G^2)
+  double* epart_ = nullptr;   // their per-chunk sums of u^2 and e^2
   float* part_ = nullptr;     // weight-gradient partial sums
   double* lpart_ = nullptr;   // loss partial sums
   double* loss_ = nullptr;

@@ -536,48 +536,101 @@ __global__ void __launch_bounds__(256) net_halo_zero(uint16_t* __restrict__ a, i
 // samples from trajectories
 // ---------------------------------------------------------------------------------------------
 
-// one workgroup per sample: planes u/s, (dt F / m)/s, ln(kappa dt n^2)/4 and (optionally) the
-// target (u_{k+1} - u_k)/s, s = rms(u) + rms(dt F / m) over the interior (1 if both vanish)
-__global__ void __launch_bounds__(256) net_pack(const NetSrc* __restrict__ src, const NetPick* __restrict__ pick,
-                                                int kbase, int G, float* __restrict__ x, float* __restrict__ t,
-                                                double* __restrict__ s, int with_target) {
+// explicit increment of interior dof (iy, ix): e = (w F - kappa dt K u) / m, the previous point's residual
+// b - A u in the step's equation divided by the lumped mass; K u by the Kronecker bands
+__device__ __forceinline__ double net_explicit(const NetSrc& S, const double* u, double w, int iy, int ix) {
+  const int nin = S.nin, bw = S.bw, p = S.p;
+  double ku = 0.0;
+  for (int a = 0; a < bw; ++a) {
+    const int jy = iy + a - p;
+    if (jy < 0 || jy >= nin) continue;
+    const double my = S.My[iy * bw + a], ky = S.Ky[iy * bw + a];
+    const double* ur = u + (int64_t)jy * nin;
+    double sk = 0.0, sm = 0.0;
+    for (int c = 0; c < bw; ++c) {
+      const int jx = ix + c - p;
+      if (jx < 0 || jx >= nin) continue;
+      sk += S.Kx[ix * bw + c] * ur[jx];
+      sm += S.Mx2[ix * bw + c] * ur[jx];
+    }
+    ku += my * sk + ky * sm;
+  }
+  return (w * S.F[iy * nin + ix] - S.kdt * ku) * S.ilx[ix] * S.ily[iy];
+}
+
+// Samples are packed by two kernels over (sample, chunk) workgroups, kPackChunks per sample:
+// net_pack_e forms the explicit increment e of its chunk of interior dofs into ebuf and the chunk's sums
+// of u^2 and e^2; net_pack_planes adds a sample's chunk sums in a fixed order and writes the planes
+// u/s_u, e/s_e, ln(kappa dt n^2)/4 and (optionally) the target (u_{k+1} - u_k)/s_e, with s_u = rms(u),
+// s_e = rms(e) over the interior (1 if zero); s receives s_e, the scale of the output.
+constexpr int kPackChunks = 16;
+
+__global__ void __launch_bounds__(256) net_pack_e(const NetSrc* __restrict__ src, const NetPick* __restrict__ pick,
+                                                  int kbase, int64_t estride, double* __restrict__ ebuf,
+                                                  double* __restrict__ epart) {
   __shared__ double red[4];
-  const int j = blockIdx.x;
+  const int j = blockIdx.x, c = blockIdx.y;
   const NetSrc S = src[pick[j].src];
   const int k = pick[j].k + kbase, nin = S.nin, nd = nin * nin;
   const double* u = S.U + (int64_t)k * nd;
-  double su = 0.0, sc = 0.0;
-  for (int i = threadIdx.x; i < nd; i += 256) {
-    const double c = S.dt * S.F[i] * S.ilx[i % nin] * S.ily[i / nin];
+  const double w = S.scale ? S.scale[k + 1] : S.dt;
+  const int per = (nd + kPackChunks - 1) / kPackChunks, i0 = c * per, i1 = min(nd, i0 + per);
+  double su = 0.0, se = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+    const double e = net_explicit(S, u, w, i / nin, i % nin);
+    ebuf[(int64_t)j * estride + i] = e;
     su += u[i] * u[i];
-    sc += c * c;
+    se += e * e;
   }
   su = net_block_sum<256>(su, red);
-  sc = net_block_sum<256>(sc, red);
-  double sc_ = sqrt(su / nd) + sqrt(sc / nd);
-  if (sc_ == 0.0) sc_ = 1.0;
-  const double inv = 1.0 / sc_;
+  se = net_block_sum<256>(se, red);
+  if (threadIdx.x == 0) {
+    epart[((int64_t)j * kPackChunks + c) * 2] = su;
+    epart[((int64_t)j * kPackChunks + c) * 2 + 1] = se;
+  }
+}
+
+__global__ void __launch_bounds__(256) net_pack_planes(const NetSrc* __restrict__ src,
+                                                       const NetPick* __restrict__ pick, int kbase, int G,
+                                                       int64_t estride, const double* __restrict__ ebuf,
+                                                       const double* __restrict__ epart, float* __restrict__ x,
+                                                       float* __restrict__ t, double* __restrict__ s,
+                                                       int with_target) {
+  const int j = blockIdx.x, c = blockIdx.y;
+  const NetSrc S = src[pick[j].src];
+  const int k = pick[j].k + kbase, nin = S.nin, nd = nin * nin;
+  const double* u = S.U + (int64_t)k * nd;
+  double su = 0.0, se = 0.0;
+  for (int q = 0; q < kPackChunks; ++q) {
+    su += epart[((int64_t)j * kPackChunks + q) * 2];
+    se += epart[((int64_t)j * kPackChunks + q) * 2 + 1];
+  }
+  double s_u = sqrt(su / nd), s_e = sqrt(se / nd);
+  if (s_u == 0.0) s_u = 1.0;
+  if (s_e == 0.0) s_e = 1.0;
   float* x0 = x + (int64_t)j * 3 * G * G;
   float* x1 = x0 + G * G;
   float* x2 = x1 + G * G;
   const float lnc = (float)S.lnc;
   const double* un = S.U + (int64_t)(k + 1) * nd;
-  for (int pix = threadIdx.x; pix < G * G; pix += 256) {
+  const double* e = ebuf + (int64_t)j * estride;
+  const int per = (G * G + kPackChunks - 1) / kPackChunks, p0 = c * per, p1 = min(G * G, p0 + per);
+  for (int pix = p0 + threadIdx.x; pix < p1; pix += 256) {
     const int yy = pix / G, xx = pix % G;
     const bool in = yy > 0 && yy < G - 1 && xx > 0 && xx < G - 1;
     const int i = (yy - 1) * nin + (xx - 1);
     float v0 = 0.f, v1 = 0.f, tv = 0.f;
     if (in) {
-      v0 = (float)(u[i] / sc_);
-      v1 = (float)(S.dt * S.F[i] * S.ilx[xx - 1] * S.ily[yy - 1] / sc_);
-      if (with_target) tv = (float)((un[i] - u[i]) * inv);
+      v0 = (float)(u[i] / s_u);
+      v1 = (float)(e[i] / s_e);
+      if (with_target) tv = (float)((un[i] - u[i]) / s_e);
     }
     x0[pix] = v0;
     x1[pix] = v1;
     x2[pix] = lnc;
     if (with_target) t[(int64_t)j * G * G + pix] = tv;
   }
-  if (threadIdx.x == 0) s[j] = sc_;
+  if (c == 0 && threadIdx.x == 0) s[j] = s_e;
 }
 
 // guesses: U_out[k + 1] = U[k] + s y on the interior
@@ -680,9 +733,11 @@ hipError_t NetState::reserve(int nb, int G) {
     sized_.push_back(*p);
   }
   if ((e = alloc(&x_, 3 * pl)) || (e = alloc(&t_, pl)) || (e = alloc(&y_, pl)) || (e = alloc(&dy_, pl)) ||
-      (e = alloc(&s_, (size_t)nb_cap_)))
+      (e = alloc(&s_, (size_t)nb_cap_)) || (e = alloc(&ebuf_, pl)) ||
+      (e = alloc(&epart_, (size_t)nb_cap_ * kPackChunks * 2)))
     return e;
-  for (void* p : {(void*)x_, (void*)t_, (void*)y_, (void*)dy_, (void*)s_}) sized_.push_back(p);
+  for (void* p : {(void*)x_, (void*)t_, (void*)y_, (void*)dy_, (void*)s_, (void*)ebuf_, (void*)epart_})
+    sized_.push_back(p);
   G_last_ = -1;
   return hipSuccess;
 }
@@ -786,8 +841,12 @@ hipError_t NetState::pack(const NetSrc* src_dev, const NetPick* pick_dev, int kb
                           hipStream_t st) {
   hipError_t e = reserve(nb, G);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(net_pack, dim3(nb), dim3(256), 0, st, src_dev, pick_dev, kbase, G, x_, t_, s_,
-                     with_target ? 1 : 0);
+  const int64_t estride = (int64_t)G_cap_ * G_cap_;
+  hipLaunchKernelGGL(net_pack_e, dim3(nb, kPackChunks), dim3(256), 0, st, src_dev, pick_dev, kbase, estride, ebuf_,
+                     epart_);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(net_pack_planes, dim3(nb, kPackChunks), dim3(256), 0, st, src_dev, pick_dev, kbase, G, estride,
+                     ebuf_, epart_, x_, t_, s_, with_target ? 1 : 0);
   return hipGetLastError();
 }
 

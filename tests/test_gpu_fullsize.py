@@ -170,8 +170,10 @@ def test_heterogeneous_batch_full_size(torch):
 @pytest.mark.timeout(900)
 def test_learned_warm_start_full_size(torch):
     """p = 3, h = 2^-6, N_t = 4096, a network trained (on the GPU, by the library's kernels) on sequential
-    trajectories of 8 other sources, then sequential stepping of an unseen source with the learned guess:
-    the trajectory equals the oracle's; V-cycles against the previous-step guess are reported."""
+    trajectories of 12 other sources, then sequential stepping of an unseen source with the learned guess:
+    the trajectory equals the oracle's, with fewer V-cycles per solve than the previous-step guess (about
+    1.03 against 1.16; the wall time per step is reported: at this size the network's per-step launches
+    cost more than the V-cycles they save)."""
     cfg = W.config("heat-p3-h64-Nt4096")
     d = cfg["instances"][0]
     say("case learned warm start p=3 h=2^-6 N_t=4096 (sequential)")
@@ -180,8 +182,8 @@ def test_learned_warm_start_full_size(torch):
     ref = Background(lambda: oracle_full(dd))
     mk = lambda n, g: pm.Solver([pm.problem(d["p"], d["n"], d["Nt"], d["kappa"], d["T"], d["domain"])] * n,
                                 pm.default_mgrit_opts(), pm.default_solver_opts(guess=g), device=0)
-    T = mk(8, 1)
-    for i in range(8):
+    T = mk(12, 1)
+    for i in range(12):
         T.set_source(i, W.random_modes(i), 0)
     Utr, _ = T.solve_sequential()
     T.net_load(W.net_init(0).astype(np.float32))
@@ -206,3 +208,4 @@ def test_learned_warm_start_full_size(torch):
         say(f"  {name}: eps={e:.2e} per-step max={ek:.2e} V-cycles/solve {st['vcycles'] / st['phi_calls']:.3f} "
             f"t={st['t_solve_s']:.2f}s")
         assert e <= EPS and ek <= EPS
+    assert out[3][1]["vcycles"] < 0.95 * out[1][1]["vcycles"]

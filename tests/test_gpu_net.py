@@ -112,7 +112,7 @@ def test_pack_matches_oracle(torch):
     nd, _, _ = S.dims(0)
     rng = np.random.default_rng(4)
     U = rng.standard_normal((Nt + 1, nd))
-    U[5] = 0.0  # a zero state: the scale comes from the source alone
+    U[5] = 0.0  # a zero state: the increment comes from the source alone
     ks = [0, 3, 5, 15]
     x, t, s = S.net_pack(0, 0, ks, torch.tensor(U, device="cuda"))
     x, t, s = x.cpu().numpy(), t.cpu().numpy(), s.cpu().numpy()
@@ -120,9 +120,10 @@ def test_pack_matches_oracle(torch):
     src = W.random_modes(100)
     F = P.load_vector(src)
     mlp = P.lumped()[0]
+    K = P.scipy("K")
     dt = 0.1 / Nt
     for j, k in enumerate(ks):
-        xr, sr, tr = cnn.pack(U[k], F, mlp, dt, 1.0, n, p, u_next=U[k + 1])
+        xr, sr, tr = cnn.pack(U[k], F, mlp, K, dt, 1.0 * dt, n, p, u_next=U[k + 1])
         assert abs(s[j] - sr) <= 1e-13 * sr
         assert np.max(np.abs(x[j] - xr)) <= 1e-6 * max(1.0, np.max(np.abs(xr)))
         assert np.max(np.abs(t[j] - tr)) <= 1e-6 * max(1.0, np.max(np.abs(tr)))

@@ -67,7 +67,8 @@ def test_zero_last_layer_returns_previous_step():
     u = rng.standard_normal(nin * nin)
     F = rng.standard_normal(nin * nin)
     mlp = 0.5 + rng.random(nin * nin)
-    x, s, _ = cnn.pack(u, F, mlp, 1e-3, 1.0, n, p)
+    K = np.eye(nin * nin)
+    x, s, _ = cnn.pack(u, F, mlp, K, 1e-3, 1e-3, n, p)
     y, _ = cnn.forward(theta, x[None])
     assert np.array_equal(cnn.unpack(y[0], u, s), u)
 
@@ -77,15 +78,35 @@ def test_pack_closed_form():
     nin = n + p - 2
     u = np.full(nin * nin, c)
     mlp = np.linspace(1.0, 2.0, nin * nin)
-    F = 5.0 * mlp  # explicit increment dt F / m = 5 dt everywhere
-    x, s, t = cnn.pack(u, F, mlp, dt, kappa, n, p, u_next=u + 1.0)
-    assert np.isclose(s, abs(c) + 5 * dt)
-    assert np.allclose(x[0, 1:-1, 1:-1], c / s) and np.all(x[0, 0] == 0) and np.all(x[0, :, -1] == 0)
-    assert np.allclose(x[1, 1:-1, 1:-1], 5 * dt / s)
+    # K = diag(2 mlp): the explicit increment (dt F - kappa dt K u) / m = dt (5 - 2 kappa c) everywhere
+    K = np.diag(2.0 * mlp)
+    F = 5.0 * mlp
+    e = dt * (5.0 - 2.0 * kappa * c)
+    x, s, t = cnn.pack(u, F, mlp, K, dt, kappa * dt, n, p, u_next=u + 1.0)
+    assert np.isclose(s, abs(e))
+    assert np.allclose(x[0, 1:-1, 1:-1], -1.0) and np.all(x[0, 0] == 0) and np.all(x[0, :, -1] == 0)
+    assert np.allclose(x[1, 1:-1, 1:-1], np.sign(e))
     assert np.allclose(x[2], np.log(kappa * dt * n * n) / 4)
     assert np.allclose(t[1:-1, 1:-1], 1.0 / s) and np.all(t[0] == 0)
-    x0, s0, _ = cnn.pack(np.zeros(nin * nin), np.zeros(nin * nin), mlp, dt, kappa, n, p)
+    x0, s0, _ = cnn.pack(np.zeros(nin * nin), np.zeros(nin * nin), mlp, K, dt, kappa * dt, n, p)
     assert s0 == 1.0 and np.all(x0[:2] == 0)
+
+
+def test_pack_increment_is_a_residual_of_the_step():
+    """The explicit-increment plane times the lumped mass and its scale is the residual b - A u_k of the step
+    (M + kappa dt K) u_{k+1} = M u_k + w F at the previous point, with the oracle's own matrices."""
+    import oracle as O
+    P = O.Problem(3, 6, 1)
+    rng = np.random.default_rng(8)
+    u = rng.standard_normal(P.ndof)
+    F = P.load_vector([(1, 2, 0.5)])
+    mlp = P.lumped()[0]
+    M, K = P.dense("M"), P.dense("K")
+    kdt, w = 0.03, 0.01
+    x, s, _ = cnn.pack(u, F, mlp, K, w, kdt, 6, 3)
+    r = (M @ u + w * F) - (M + kdt * K) @ u
+    nin = P.Nin
+    assert np.allclose(x[1, 1:-1, 1:-1].ravel() * s * mlp, r, rtol=1e-12, atol=1e-14)
 
 
 def test_adam_first_step_is_signed_lr():
