@@ -241,11 +241,13 @@ pmgrit_status pmgrit_host_coarse_solve(const pmgrit_handle* h, int32_t inst, int
 
 /* Learned warm start (not part of the paper).  A 4-layer 3x3 convolutional network over the
  * G x G tensor-product coefficient grid (G = n + p, the Dirichlet ring included) with channels
- * 3 -> 32 -> 32 -> 32 -> 1, zero padding and ReLU after the first three layers.  Input planes of
- * a sample (step k -> k + 1 of an instance, time level l): u_k / s, (dt_l F / m) / s with m the
- * row-sum-lumped mass, and ln(kappa dt_l n^2) / 4; s = rms(u_k) + rms(dt_l F / m) over the
- * interior (1 if both vanish).  Output y: guess u_{k+1} = u_k + s y on the interior; training
- * target t = (u_{k+1} - u_k) / s; loss = mean over samples and interior points of (y - t)^2.
+ * 3 -> 32 -> 32 -> 32 -> 1, zero padding and ReLU after the first three layers.  Input planes of a
+ * sample (step k -> k + 1 of an instance, time level l): u_k / s_u; e / s_e with
+ * e = (w F - kappa dt_l K u_k) / m, the residual of the step's equation at the previous point divided by
+ * the row-sum-lumped mass m (w: the step's source weight, dt_l at coarse levels); and
+ * ln(kappa dt_l n^2) / 4; s_u = rms(u_k), s_e = rms(e) over the interior (1 if zero).  Output y: guess
+ * u_{k+1} = u_k + s_e y on the interior; training target t = (u_{k+1} - u_k) / s_e; loss = mean over
+ * samples and interior points of (y - t)^2.
  * Weights, inputs and hidden activations (and hidden gradients) are BF16 with FP32 accumulation.
  * Parameters: a flat float array, per layer weights [cout][cin][3][3] then bias [cout]
  * (pmgrit_net_nparams() floats, FP32 master copy).  A handle holds one network. */
