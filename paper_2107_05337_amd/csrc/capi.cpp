@@ -779,6 +779,15 @@ static void add_window(LdsPlan& plan, int& off, int mask, int vt, int winw, int 
     plan.off_stage = off;
     off += st;
   }
+  // y in global memory: the rest of the budget stages the band passes (at least kBandStageMin)
+  if (!(mask & kY)) {
+    const int sz = (dev_lds - off) / 16 * 16;
+    if (sz >= kBandStageMin) {
+      plan.off_bst = off;
+      plan.bst_bytes = sz;
+      off += sz;
+    }
+  }
 }
 
 static void lds_plan(int nmax, int n1max, int maxrows, int vt, int ka, int dev_lds, int winw, int& mask, int& bytes,

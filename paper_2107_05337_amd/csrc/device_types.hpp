@@ -23,6 +23,7 @@ constexpr int kSbufWords = 320;
 // LDS staging area of the exact p = 1 solve's dense transforms (doubles)
 constexpr int kStageDoubles = 2048;
 constexpr int kStageMinN1 = 128;  // used from this many p = 1 nodes per direction up
+constexpr int kBandStageMin = 16 * 1024;  // smallest LDS staging area of the band passes (bytes)
 // LDS per workgroup of gfx950 (160 KiB)
 constexpr int kLdsBytes = 160 * 1024;
 // default row-block size of the triangular solves
@@ -165,6 +166,8 @@ struct LdsPlan {
   int off_win;    // y not in LDS: LDS window of the triangular solves (-1: none)
   int zwin;       // index (in V-cycle words) of the window's always-zero word
   int off_stage = -1;  // staging area of the p = 1 transforms, kStageDoubles (-1: none)
+  int off_bst = -1;    // y not in LDS: staging area of the band passes (-1: none)
+  int bst_bytes = 0;   // its size
 };
 
 enum : int { kY = 1, kD = 2, kS = 4, kX = 8 };

@@ -32,6 +32,9 @@ template <class T>
 __device__ __forceinline__ const G<T>* gp(const T* p) {
   return (const G<T>*)p;
 }
+// LDS pointer type
+template <class T>
+using L3 = __attribute__((address_space(3))) T;
 
 // Kernel builds: OCC 1 runs 512 threads (4 lanes per triangular-solve row, 128 row slots per
 // level, a 256-register budget per thread), OCC 2 the same limited to 128 registers (two
@@ -249,6 +252,256 @@ __device__ __forceinline__ double pass_y2(int ncols, int nin, const BandDev& B1d
   return part;
 }
 
+// LDS staging of the band passes whose vectors are in global memory (y not in LDS): per chunk of
+// rows the band entries and the input rows are copied into LDS by every thread, kStU loads in
+// flight per thread, and the outputs are formed from LDS.  The direct passes pay one global
+// load latency per output row and thread in sequence; here a chunk costs a few.  Each output is
+// summed in the same order and with the same operations as in the direct passes, and each
+// thread forms the same outputs (index = thread mod NT), so results agree bitwise.  p = null,
+// or an area too small for the pass: the direct pass.  Vectors are read through generic
+// pointers (any of them may be in LDS).
+struct Stg {
+  unsigned char* p = nullptr;
+  int bytes = 0;
+};
+constexpr int kStU = 8;
+// the builds that stage: y in global memory, the 512-thread build with the full register budget
+template <int MASK, int OCC>
+struct Staged {
+  static constexpr bool value = !(MASK & kY) && OCC == 1;
+};
+
+__device__ __forceinline__ int al16(int b) { return (b + 15) / 16 * 16; }
+
+template <int NT, typename T, typename S>
+__device__ __forceinline__ void stage_copy(L3<T>* dst, const S* src, int n) {
+  for (int e0 = threadIdx.x; e0 < n; e0 += kStU * NT) {
+    T v[kStU];
+#pragma unroll
+    for (int u = 0; u < kStU; ++u) {
+      const int e = e0 + u * NT;
+      v[u] = e < n ? (T)src[e] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStU; ++u) {
+      const int e = e0 + u * NT;
+      if (e < n) dst[e] = v[u];
+    }
+  }
+}
+
+// first index >= base that this thread owns in a pass over outputs 0, 1, ... (index mod NT)
+template <int NT>
+__device__ __forceinline__ int own_from(int base) {
+  return ((int)threadIdx.x - base % NT + NT) % NT;
+}
+
+// pass_x with staging (the direct pass when one input row and the band do not fit)
+template <int NT, typename AT, typename IT, typename OT>
+__device__ void pass_x_st(int nrows, int nin, const BandDev& Bd, const IT* in, OT* out, Stg st) {
+  const int nout = Bd.rows, w = Bd.w, lo = Bd.lo;
+  const int bw = al16(nout * w * (int)sizeof(AT));
+  const int RC = (st.bytes - bw) / (nin * (int)sizeof(IT));
+  if (!st.p || RC < 1) {
+    pass_x<NT, AT>(nrows, nin, Bd, in, out);
+    return;
+  }
+  L3<AT>* bs = (L3<AT>*)st.p;
+  L3<IT>* rows = (L3<IT>*)(st.p + bw);
+  __syncthreads();  // earlier readers of the staging area
+  stage_copy<NT>(bs, band_ptr<AT>(Bd), nout * w);
+  for (int r0 = 0; r0 < nrows; r0 += RC) {
+    const int rc = min(RC, nrows - r0);
+    if (r0 > 0) __syncthreads();
+    stage_copy<NT>(rows, in + (int64_t)r0 * nin, rc * nin);
+    __syncthreads();
+    for (int t = threadIdx.x; t < rc * nout; t += NT) {
+      const int rr = t / nout, o = t - rr * nout;
+      AT s = 0;
+      for (int d = 0; d < w; ++d) {
+        int j = o + lo + d;
+        j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+        s += bs[o * w + d] * (AT)rows[rr * nin + j];
+      }
+      out[(int64_t)(r0 + rr) * nout + o] = (OT)s;
+    }
+  }
+}
+
+// chunk geometry of the second-direction passes: rows [o0, o0 + rc) of the output need band rows
+// o0 .. o0 + rc - 1 and input rows jlo .. jhi
+__device__ __forceinline__ void y_chunk(int o0, int rc, int nin, int lo, int w, int& jlo, int& jhi) {
+  const int a = o0 + lo, b = o0 + rc - 1 + lo + w - 1;
+  jlo = a < 0 ? 0 : (a >= nin ? nin - 1 : a);
+  jhi = b < 0 ? 0 : (b >= nin ? nin - 1 : b);
+}
+
+// pass_y with staging (the direct pass when w input rows and one band row do not fit)
+template <int NT, typename AT, typename TT, typename ZT, typename OT>
+__device__ double pass_y_st(int ncols, int nin, const BandDev& Bd, const TT* T, AT alpha, const ZT* z, AT beta,
+                            bool acc, const double* scy, const double* scx, OT* out, Stg st) {
+  const int nout = Bd.rows, w = Bd.w, lo = Bd.lo;
+  const int rowb = ncols * (int)sizeof(TT);
+  const int RC = min(nout, (st.bytes - 16 - (w - 1) * rowb) / (rowb + w * (int)sizeof(AT)));
+  if (!st.p || RC < 1) return pass_y<NT, AT>(ncols, nin, Bd, T, alpha, z, beta, acc, scy, scx, out);
+  double part = 0.0;
+  const int bw = al16(RC * w * (int)sizeof(AT));
+  L3<AT>* bs = (L3<AT>*)st.p;
+  L3<TT>* rows = (L3<TT>*)(st.p + bw);
+  const G<AT>* __restrict__ B = band_ptr<AT>(Bd);
+  __syncthreads();
+  for (int o0 = 0; o0 < nout; o0 += RC) {
+    const int rc = min(RC, nout - o0);
+    int jlo, jhi;
+    y_chunk(o0, rc, nin, lo, w, jlo, jhi);
+    if (o0 > 0) __syncthreads();
+    stage_copy<NT>(bs, B + (int64_t)o0 * w, rc * w);
+    stage_copy<NT>(rows, T + (int64_t)jlo * ncols, (jhi - jlo + 1) * ncols);
+    __syncthreads();
+    const int base = o0 * ncols, tot = rc * ncols;
+    for (int t0 = own_from<NT>(base); t0 < tot; t0 += kStU * NT) {
+      // the chunk's other operands, all requested before the first output is formed
+      AT zv[kStU], av[kStU];
+      double sc[kStU];
+#pragma unroll
+      for (int u = 0; u < kStU; ++u) {
+        const int t = t0 + u * NT;
+        const bool ok = t < tot;
+        const int o = o0 + t / ncols, c = t - (t / ncols) * ncols;
+        const int64_t ti = (int64_t)base + t;
+        zv[u] = (z && ok) ? (AT)z[ti] : (AT)0;
+        av[u] = (acc && ok) ? (AT)out[ti] : (AT)0;
+        sc[u] = (scy && ok) ? gp(scy)[o] * gp(scx)[c] : 1.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kStU; ++u) {
+        const int t = t0 + u * NT;
+        if (t < tot) {
+          const int oo = t / ncols, c = t - oo * ncols, o = o0 + oo;
+          AT s = 0;
+          for (int d = 0; d < w; ++d) {
+            int j = o + lo + d;
+            j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+            s += bs[oo * w + d] * (AT)rows[(j - jlo) * ncols + c];
+          }
+          AT v = alpha * s;
+          if (scy) v *= (AT)sc[u];
+          if (z) v += beta * zv[u];
+          if (acc) v += av[u];
+          out[(int64_t)base + t] = (OT)v;
+          part += (double)v * (double)v;
+        }
+      }
+    }
+  }
+  return part;
+}
+
+// pass_x2 with staging (both bands, one copy of each input row; the direct pass when they do not fit)
+template <int NT, typename AT, typename IT, typename OT>
+__device__ void pass_x2_st(int nrows, int nin, const BandDev& B1d, const BandDev& B2d, const IT* in, OT* out1,
+                           OT* out2, Stg st) {
+  const int nout = B1d.rows, w = B1d.w, lo = B1d.lo;
+  const int bw = al16(nout * w * (int)sizeof(AT));
+  const int RC = (st.bytes - 2 * bw) / (nin * (int)sizeof(IT));
+  if (!st.p || RC < 1) {
+    pass_x2<NT, AT>(nrows, nin, B1d, B2d, in, out1, out2);
+    return;
+  }
+  L3<AT>* b1 = (L3<AT>*)st.p;
+  L3<AT>* b2 = (L3<AT>*)(st.p + bw);
+  L3<IT>* rows = (L3<IT>*)(st.p + 2 * bw);
+  __syncthreads();
+  stage_copy<NT>(b1, band_ptr<AT>(B1d), nout * w);
+  stage_copy<NT>(b2, band_ptr<AT>(B2d), nout * w);
+  for (int r0 = 0; r0 < nrows; r0 += RC) {
+    const int rc = min(RC, nrows - r0);
+    if (r0 > 0) __syncthreads();
+    stage_copy<NT>(rows, in + (int64_t)r0 * nin, rc * nin);
+    __syncthreads();
+    for (int t = threadIdx.x; t < rc * nout; t += NT) {
+      const int rr = t / nout, o = t - rr * nout;
+      AT s1 = 0, s2 = 0;
+      for (int d = 0; d < w; ++d) {
+        int j = o + lo + d;
+        j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+        const AT v = (AT)rows[rr * nin + j];
+        s1 += b1[o * w + d] * v;
+        s2 += b2[o * w + d] * v;
+      }
+      out1[(int64_t)(r0 + rr) * nout + o] = (OT)s1;
+      out2[(int64_t)(r0 + rr) * nout + o] = (OT)s2;
+    }
+  }
+}
+
+// pass_y2 with staging (the direct pass when they do not fit)
+template <int NT, typename AT, typename TT, typename ZT, typename OT>
+__device__ double pass_y2_st(int ncols, int nin, const BandDev& B1d, const BandDev& B2d, const TT* T1,
+                             const TT* T2, AT a1, AT a2, const ZT* z, AT beta, OT* out, Stg st) {
+  const int nout = B1d.rows, w = B1d.w, lo = B1d.lo;
+  const int rowb = ncols * (int)sizeof(TT);
+  const int RC = min(nout, (st.bytes - 64 - 2 * (w - 1) * rowb) / (2 * rowb + 2 * w * (int)sizeof(AT)));
+  if (!st.p || RC < 1) return pass_y2<NT, AT>(ncols, nin, B1d, B2d, T1, T2, a1, a2, z, beta, out);
+  double part = 0.0;
+  const int bw = al16(RC * w * (int)sizeof(AT));
+  L3<AT>* c1 = (L3<AT>*)st.p;
+  L3<AT>* c2 = (L3<AT>*)(st.p + bw);
+  const G<AT>* __restrict__ B1 = band_ptr<AT>(B1d);
+  const G<AT>* __restrict__ B2 = band_ptr<AT>(B2d);
+  __syncthreads();
+  for (int o0 = 0; o0 < nout; o0 += RC) {
+    const int rc = min(RC, nout - o0);
+    int jlo, jhi;
+    y_chunk(o0, rc, nin, lo, w, jlo, jhi);
+    const int nr = jhi - jlo + 1;
+    L3<TT>* r1 = (L3<TT>*)(st.p + 2 * bw);
+    L3<TT>* r2 = (L3<TT>*)(st.p + 2 * bw + al16(nr * rowb));
+    if (o0 > 0) __syncthreads();
+    stage_copy<NT>(c1, B1 + (int64_t)o0 * w, rc * w);
+    stage_copy<NT>(c2, B2 + (int64_t)o0 * w, rc * w);
+    stage_copy<NT>(r1, T1 + (int64_t)jlo * ncols, nr * ncols);
+    stage_copy<NT>(r2, T2 + (int64_t)jlo * ncols, nr * ncols);
+    __syncthreads();
+    const int base = o0 * ncols, tot = rc * ncols;
+    for (int t0 = own_from<NT>(base); t0 < tot; t0 += kStU * NT) {
+      AT zv[kStU];
+#pragma unroll
+      for (int u = 0; u < kStU; ++u) {
+        const int t = t0 + u * NT;
+        zv[u] = (z && t < tot) ? (AT)z[(int64_t)base + t] : (AT)0;
+      }
+#pragma unroll
+      for (int u = 0; u < kStU; ++u) {
+        const int t = t0 + u * NT;
+        if (t < tot) {
+          const int oo = t / ncols, c = t - oo * ncols, o = o0 + oo;
+          AT s1 = 0, s2 = 0;
+          for (int d = 0; d < w; ++d) {
+            int j = o + lo + d;
+            j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+            s1 += c1[oo * w + d] * (AT)r1[(j - jlo) * ncols + c];
+            s2 += c2[oo * w + d] * (AT)r2[(j - jlo) * ncols + c];
+          }
+          AT v = a1 * s1;
+          if (z) v += beta * zv[u];
+          v += a2 * s2;
+          out[(int64_t)base + t] = (OT)v;
+          part += (double)v * (double)v;
+        }
+      }
+    }
+  }
+  return part;
+}
+
+// the two terms of A_l have bands of equal shape and fit the fused passes
+template <int NT>
+__device__ __forceinline__ bool fusable(const InstDev& I, const LevelDev& L) {
+  return L.X1.w == I.Mx2.w && L.X1.lo == I.Mx2.lo && I.My.w == I.Ky.w && I.My.lo == I.Ky.lo && L.X1.w <= kBandMax &&
+         I.My.w <= kBandMax && I.Mx2.rows <= NT;
+}
+
 // out = beta z - A_l x with A_l = My (x) X1 + c Ky (x) Mx2 (temp: nin x nin scratch, may not
 // alias x or out).  Returns this thread's share of ||out||^2.
 // (OCC only separates the instances called from the two-workgroups-per-CU kernels, which get
@@ -259,8 +512,7 @@ __device__ double apply_A(const InstDev& I, const LevelDev& L, const XT* x, cons
   if constexpr (sizeof(TT) == 4) {
     // FP32 temporaries: tmp is an FP64-sized slot and holds both, so the two terms of A_l take
     // one first- and one second-direction pass
-    if (L.X1.w == I.Mx2.w && L.X1.lo == I.Mx2.lo && I.My.w == I.Ky.w && I.My.lo == I.Ky.lo &&
-        L.X1.w <= kBandMax && I.My.w <= kBandMax && I.Mx2.rows <= NT) {
+    if (fusable<NT>(I, L)) {
       TT* t2 = tmp + n * n;
       pass_x2<NT, AT>(n, n, L.X1, I.Mx2, x, tmp, t2);
       __syncthreads();
@@ -281,6 +533,33 @@ __device__ double apply_A(const InstDev& I, const LevelDev& L, const XT* x, cons
   return part;
 }
 
+// apply_A through LDS staging (st.p set: the vectors are in global memory).  Same roundings as
+// apply_A: the fused form where apply_A fuses (FP32 temporaries, both in tmp) or where the caller
+// gives a second FP64 temporary tmp2, else the four-pass form.
+template <int NT, typename AT, typename XT, typename ZT, typename OT, typename TT>
+__device__ double apply_A_st(const InstDev& I, const LevelDev& L, const XT* x, const ZT* z, OT* out, TT* tmp,
+                             Stg st, TT* tmp2 = nullptr) {
+  const int n = I.nin;
+  TT* t2 = sizeof(TT) == 4 ? tmp + n * n : tmp2;
+  if (t2 && fusable<NT>(I, L)) {
+    pass_x2_st<NT, AT>(n, n, L.X1, I.Mx2, x, tmp, t2, st);
+    __syncthreads();
+    const double part = pass_y2_st<NT, AT>(n, n, I.My, I.Ky, tmp, (const TT*)t2, (AT)-1, (AT)(-L.c), z, (AT)1, out, st);
+    __syncthreads();
+    return part;
+  }
+  pass_x_st<NT, AT>(n, n, L.X1, x, tmp, st);
+  __syncthreads();
+  pass_y_st<NT, AT>(n, n, I.My, tmp, (AT)-1, z, (AT)1, false, nullptr, nullptr, out, st);
+  __syncthreads();
+  pass_x_st<NT, AT>(n, n, I.Mx2, x, tmp, st);
+  __syncthreads();
+  double part =
+      pass_y_st<NT, AT>(n, n, I.Ky, tmp, (AT)(-L.c), (const ZT*)nullptr, (AT)0, true, nullptr, nullptr, out, st);
+  __syncthreads();
+  return part;
+}
+
 // ---------------------------------------------------------------------------------------
 // blocked level-scheduled triangular solves
 // ---------------------------------------------------------------------------------------
@@ -288,8 +567,6 @@ __device__ double apply_A(const InstDev& I, const LevelDev& L, const XT* x, cons
 // Both paths solve T y = in (T = L with unit diagonal, or U), writing y (which may alias in),
 // level by level over a blocked level schedule (blocks of consecutive rows, at most kDenseMax;
 // a level is a set of independent blocks).
-template <class T>
-using L3 = __attribute__((address_space(3))) T;
 
 // sum over the 4 lanes of a quad with DPP lane permutes (no LDS round trip)
 template <int CTRL>
@@ -1004,9 +1281,18 @@ __device__ __forceinline__ void hmg_wcycle(const InstDev& I, const LevelDev& L, 
 // Buffers: y (nin^2 doubles, LDS first), s (>= max(nin^2 VT, n1^2 doubles)), d (nin^2 VT).
 template <typename VT, int MASK, int OCC, bool EXT>
 __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, const VT* r, VT* d, VT* y, VT* s,
-                       VT* sbuf, int ka, int zidx, VT* win, int zwin, int coarse, double* hw, double* stage) {
+                       VT* sbuf, int ka, int zidx, VT* win, int zwin, int coarse, double* hw, double* stage,
+                       Stg bst) {
   constexpr bool YL = MASK & kY;
   constexpr int NT = Build<OCC>::NT;
+  constexpr bool ST = Staged<MASK, OCC>::value;
+  // s = r - A_l d, staged through LDS when the vectors are in global memory
+  auto resid = [&]() {
+    if constexpr (!ST)
+      apply_A<NT, VT, OCC>(I, L, d, r, s, y);
+    else
+      apply_A_st<NT, VT>(I, L, d, r, s, y, bst);
+  };
   const int n = I.ndof;
   // the 1024-thread build reads the factors' slot tables laid out for 8 lanes per row
   const TriDev& TL = Build<OCC>::TG == 8 ? L.L8 : L.L;
@@ -1017,19 +1303,25 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
   for (int i = threadIdx.x; i < n; i += NT) d[i] = y[i];
   __syncthreads();
   for (int m = 1; m < nu1; ++m) {
-    apply_A<NT, VT, OCC>(I, L, d, r, s, y);
+    resid();
     trsv<VT, YL, !(MASK & kS), OCC>(TL, ka, zidx, s, y, sbuf, win, zwin);
     trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf, win, zwin);
     for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
     __syncthreads();
   }
   // step 2: residual restricted to p = 1, r1 = (M1^L)^{-1} P^T (r - A d); r1 lands in s
-  apply_A<NT, VT, OCC>(I, L, d, r, s, y);
+  resid();
   double* c1 = (double*)s;
   double* c2 = (double*)y;
-  pass_x<NT, VT>(I.nin, I.nin, I.PxT, s, y);  // nin rows x n1 columns
-  __syncthreads();
-  pass_y<NT, VT>(I.n1, I.nin, I.PyT, y, (VT)1, (const VT*)nullptr, (VT)0, false, I.il1_y, I.il1_x, c1);
+  if constexpr (!ST) {
+    pass_x<NT, VT>(I.nin, I.nin, I.PxT, s, y);  // nin rows x n1 columns
+    __syncthreads();
+    pass_y<NT, VT>(I.n1, I.nin, I.PyT, y, (VT)1, (const VT*)nullptr, (VT)0, false, I.il1_y, I.il1_x, c1);
+  } else {
+    pass_x_st<NT, VT>(I.nin, I.nin, I.PxT, s, y, bst);
+    __syncthreads();
+    pass_y_st<NT, VT>(I.n1, I.nin, I.PyT, y, (VT)1, (const VT*)nullptr, (VT)0, false, I.il1_y, I.il1_x, c1, bst);
+  }
   __syncthreads();
   // step 3: p = 1 solve (FP64), exact or by one h-multigrid W-cycle
   if (EXT && coarse == 1) {
@@ -1043,13 +1335,19 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
     if (stage && I.n1 >= kStageMinN1 && win && threadIdx.x == 0) win[zwin] = (VT)0;
   }
   // step 4: prolongation and update d += (Mp^L)^{-1} P e1
-  pass_x<NT, VT>(I.n1, I.n1, I.Px, c1, y);  // n1 rows x nin columns
-  __syncthreads();
-  pass_y<NT, VT>(I.nin, I.n1, I.Py, y, (VT)1, (const VT*)nullptr, (VT)0, true, I.ilp_y, I.ilp_x, d);
+  if constexpr (!ST) {
+    pass_x<NT, VT>(I.n1, I.n1, I.Px, c1, y);  // n1 rows x nin columns
+    __syncthreads();
+    pass_y<NT, VT>(I.nin, I.n1, I.Py, y, (VT)1, (const VT*)nullptr, (VT)0, true, I.ilp_y, I.ilp_x, d);
+  } else {
+    pass_x_st<NT, VT>(I.n1, I.n1, I.Px, c1, y, bst);
+    __syncthreads();
+    pass_y_st<NT, VT>(I.nin, I.n1, I.Py, y, (VT)1, (const VT*)nullptr, (VT)0, true, I.ilp_y, I.ilp_x, d, bst);
+  }
   __syncthreads();
   // step 5: nu2 post-smoothing steps d += S (r - A d)
   for (int m = 0; m < nu2; ++m) {
-    apply_A<NT, VT, OCC>(I, L, d, r, s, y);
+    resid();
     trsv<VT, YL, !(MASK & kS), OCC>(TL, ka, zidx, s, y, sbuf, win, zwin);
     trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf, win, zwin);
     for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
@@ -1134,6 +1432,14 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
   // use at once); the builds limited to 128 registers keep the direct transforms
   double* stage = (plan.off_stage >= 0 && (OCC == 1 || OCC == 4)) ? (double*)(smem + plan.off_stage) : nullptr;
   if (win && threadIdx.x == 0) win[plan.zwin] = (VT)0;
+  // LDS staging area of the band passes when y is in global memory
+  Stg bst;
+  if constexpr (Staged<MASK, OCC>::value) {
+    if (plan.off_bst >= 0) {
+      bst.p = smem + plan.off_bst;
+      bst.bytes = plan.bst_bytes;
+    }
+  }
   for (int i = threadIdx.x; i < kSbufWords; i += NT) sbuf[i] = (VT)0;
   double* Vl = P.vtab ? P.vtab[job.inst * kMaxLevels + job.level] : nullptr;
   const double* Gl = (P.gtab && job.level > 0) ? P.gtab[job.inst * kMaxLevels + job.level] : nullptr;
@@ -1156,7 +1462,12 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
     } else {
       const double* vk = Vl + (int64_t)k * n;
       const double c = job.level == 0 ? scale[k + 1] : 0.0;
-      if (!EXT || L.cb == 0.0) {  // implicit Euler: B_l = M
+      if ((!EXT || L.cb == 0.0) && Staged<MASK, OCC>::value) {  // implicit Euler, staged passes
+        pass_x_st<NT, double>(I.nin, I.nin, I.Mx, vk, yd, bst);
+        __syncthreads();
+        pass_y_st<NT, double>(I.nin, I.nin, I.My, yd, 1.0, job.level == 0 ? Fv : (const double*)nullptr, c, false,
+                              nullptr, nullptr, b, bst);
+      } else if (!EXT || L.cb == 0.0) {  // implicit Euler: B_l = M
         pass_x<NT, double>(I.nin, I.nin, I.Mx, vk, yd);
         __syncthreads();
         pass_y<NT, double>(I.nin, I.nin, I.My, yd, 1.0, job.level == 0 ? Fv : (const double*)nullptr, c, false,
@@ -1212,13 +1523,20 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
       constexpr bool FUSE = sizeof(VT) == 8 ? (MASK & kD) != 0 : ((MASK & kD) && (MASK & kS));
       bool fused = false;
       if constexpr (FUSE) {
-        if (L.X1.w == I.Mx2.w && L.X1.lo == I.Mx2.lo && I.My.w == I.Ky.w && I.My.lo == I.Ky.lo &&
-            L.X1.w <= kBandMax && I.My.w <= kBandMax && I.Mx2.rows <= NT) {
+        if (fusable<NT>(I, L)) {
           double* t2 = (double*)(smem + plan.off_d);
           pass_x2<NT, double>(I.nin, I.nin, L.X1, I.Mx2, x, yd, t2);
           __syncthreads();
           part = pass_y2<NT, double>(I.nin, I.nin, I.My, I.Ky, yd, (const double*)t2, -1.0, -L.c, b, 1.0, r);
           __syncthreads();
+          fused = true;
+        }
+      }
+      if constexpr (Staged<MASK, OCC>::value) {
+        // y in global memory: staged passes, fused through the d slot when it is in global memory
+        // (free here), written straight into r
+        if (!fused && bst.p && !(MASK & kD) && (sizeof(VT) == 8 || fusable<NT>(I, L))) {
+          part = apply_A_st<NT, double>(I, L, x, b, r, yd, bst, ws + 4 * nm);
           fused = true;
         }
       }
@@ -1243,7 +1561,7 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
         break;
       }
       vcycle<VT, MASK, OCC, EXT>(I, L, P.nu1, P.nu2, r, d, y, s, sbuf, plan.ka, plan.zidx, win, plan.zwin, P.coarse,
-                                 ws + P.hmg_off, stage);
+                                 ws + P.hmg_off, stage, bst);
       for (int i = threadIdx.x; i < n; i += NT) x[i] += (double)d[i];
       __syncthreads();
       ++cyc;
