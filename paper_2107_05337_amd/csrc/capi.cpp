@@ -722,6 +722,15 @@ static Dense transpose_dense(const Dense& A) {
   return T;
 }
 
+// an n x n table stored by mode (v[k * n + i]) rewritten by node (out[i * n + k])
+static std::vector<double> node_major(const std::vector<double>& v) {
+  const size_t n = (size_t)std::llround(std::sqrt((double)v.size()));
+  std::vector<double> out(v.size());
+  for (size_t k = 0; k < n; ++k)
+    for (size_t i = 0; i < n; ++i) out[i * n + k] = v[k * n + i];
+  return out;
+}
+
 // 1 / (full row sums) on the interior rows: the inverse lumped mass of one direction
 static std::vector<double> inv_rowsum_interior(const Dense& A) {
   std::vector<double> out;
@@ -1083,14 +1092,15 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
       TRY(upload_tri(H, Lh.SU, Ld.U, zidx, G.rw, 4, wl, I.Nin));
       TRY(upload_tri(H, Lh.SL, Ld.L8, yl ? zidx : -1, G.rw8, 8, 0, I.Nin));
       TRY(upload_tri(H, Lh.SU, Ld.U8, yl ? zidx : -1, G.rw8, 8, 0, I.Nin));
-      TRY(upload_vec(H, Lh.tl, &d));
+      // the Thomas data node-major on the device (one thread per mode reads consecutive words)
+      TRY(upload_vec(H, node_major(Lh.tl), &d));
       Ld.tl = d;
-      TRY(upload_vec(H, Lh.tdinv, &d));
+      TRY(upload_vec(H, node_major(Lh.tdinv), &d));
       Ld.tdinv = d;
       if (H->so.coarse == 1) {
-        TRY(upload_vec(H, Lh.htl, &d));
+        TRY(upload_vec(H, node_major(Lh.htl), &d));
         Ld.htl = d;
-        TRY(upload_vec(H, Lh.htd, &d));
+        TRY(upload_vec(H, node_major(Lh.htd), &d));
         Ld.htd = d;
       }
       if (H->so.solver == 1) {  // diag(A_l) for the Jacobi-preconditioned CG

@@ -22,7 +22,6 @@ constexpr int kWinBlock = 128;
 constexpr int kSbufWords = 320;
 // LDS staging area of the exact p = 1 solve's dense transforms (doubles)
 constexpr int kStageDoubles = 2048;
-constexpr int kStageMinN1 = 128;  // used from this many p = 1 nodes per direction up
 constexpr int kBandStageMin = 16 * 1024;  // smallest LDS staging area of the band passes (bytes)
 // LDS per workgroup of gfx950 (160 KiB)
 constexpr int kLdsBytes = 160 * 1024;
@@ -81,9 +80,9 @@ struct LevelDev {
   BandDev XB;          // first-direction factor of B_l's first term: Mx - cb Kx (cb != 0 only)
   TriDev L, U;         // ILUT(A_l) factors (slot tables for 4 lanes per row)
   TriDev L8, U8;       // the same factors, slot tables for 8 lanes per row
-  const double* tl;    // exact p = 1 solve: Thomas multipliers per mode [n1][n1]
-  const double* tdinv; //                    inverse pivots per mode [n1][n1]
-  const double* htl;   // h-multigrid p = 1 solve: Thomas data of the coarsest h-level [n1c][n1c]
+  const double* tl;    // exact p = 1 solve: Thomas multipliers, node-major [node][mode] (n1 x n1)
+  const double* tdinv; //                    inverse pivots, node-major
+  const double* htl;   // h-multigrid p = 1 solve: Thomas data of the coarsest h-level, node-major
   const double* htd;
   const double* dgA;   // diag(A_l) (ndof), for Jacobi-preconditioned CG
 };

@@ -44,6 +44,8 @@ using L3 = __attribute__((address_space(3))) T;
 template <int OCC>
 struct Build {
   static constexpr int NT = OCC == 3 ? 1024 : 512, TG = (OCC == 3 || OCC == 4) ? 8 : 4;
+  // wave tile width (16 x 16 blocks) of the p = 1 transforms: narrower where registers are scarce
+  static constexpr int GBC = (OCC == 1 || OCC == 4) ? 4 : 1;
 };
 
 template <int G, typename T>
@@ -920,143 +922,173 @@ __device__ __forceinline__ void trsv(const TriDev& T, int ka, int zidx, const VT
 // exact p = 1 solve: fast diagonalisation c = V diag-solve(V^T c), one symmetric tridiagonal
 // system per mode of the second direction (Thomas, precomputed LDL^T).  c1 in / out, c2 temp.
 // ---------------------------------------------------------------------------------------
-// dense transform over the second direction, out[a][ix] = sum_b W(a, b) in[b][ix] for a, ix < n1,
-// with W(a, b) = V[b][a] (transposed) or V[a][b]: T x T output tiles per thread (T = 4 with 512
-// threads, 2 with 1024: about one tile per thread at the sizes here, and few registers), so
-// each loaded V entry and input entry serves T products; two steps of b per trip keep the V
-// loads (global) of both in flight together
-template <int NT, bool TRANS>
-__device__ __forceinline__ void coarse_transform(int n1, const G<double>* __restrict__ V, const double* in,
-                                                 double* out) {
-  constexpr int T = NT >= 1024 ? 2 : 4;
-  const int nt = (n1 + T - 1) / T, tiles = nt * nt;
-  for (int t = threadIdx.x; t < tiles; t += NT) {
-    const int a0 = (t / nt) * T, x0 = (t % nt) * T;
-    double acc[T][T] = {};
-    int ia[T], ix[T];
-#pragma unroll
-    for (int u = 0; u < T; ++u) {
-      ia[u] = a0 + u < n1 ? a0 + u : n1 - 1;  // clamped: rows / columns past n1 are not stored
-      ix[u] = x0 + u < n1 ? x0 + u : n1 - 1;
-    }
-    int b = 0;
-    for (; b + 2 <= n1; b += 2) {
-      double w[2][T], v[2][T];
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int u = 0; u < T; ++u) {
-          w[s][u] = TRANS ? V[(b + s) * n1 + ia[u]] : V[ia[u] * n1 + b + s];
-          v[s][u] = in[(b + s) * n1 + ix[u]];
-        }
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int u = 0; u < T; ++u)
-#pragma unroll
-          for (int q = 0; q < T; ++q) acc[u][q] += w[s][u] * v[s][q];
-    }
-    for (; b < n1; ++b) {
-      double w[T], v[T];
-#pragma unroll
-      for (int u = 0; u < T; ++u) {
-        w[u] = TRANS ? V[b * n1 + ia[u]] : V[ia[u] * n1 + b];
-        v[u] = in[b * n1 + ix[u]];
-      }
-#pragma unroll
-      for (int u = 0; u < T; ++u)
-#pragma unroll
-        for (int q = 0; q < T; ++q) acc[u][q] += w[u] * v[q];
-    }
-#pragma unroll
-    for (int u = 0; u < T; ++u)
-#pragma unroll
-      for (int q = 0; q < T; ++q)
-        if (a0 + u < n1 && x0 + q < n1) out[(a0 + u) * n1 + x0 + q] = acc[u][q];
-  }
+// Dense transforms of the fast diagonalisation on the matrix cores (FP64 MFMA, 16 x 16 x 4):
+//   out(a, x) = sum_b W(a, b) In(b, x)   for a, x < n1,
+// W(a, b) = V[b][a] (WT) or V[a][b]; In(b, x) = in[x][b] (IT) or in[b][x]; the result is stored at
+// out[x][a] (OT) or out[a][x].  Workgroup tiles of 128 x TX outputs (TX = 16 BC times the waves / 4),
+// each wave a 32 x 16 BC part (2 x BC blocks of 16 x 16).  With an LDS staging area of
+// kStageDoubles the contraction runs in chunks of KC = 8 staged in LDS (with BC = 4 the next chunk's
+// loads are held in registers while the current one is multiplied); without one each wave reads its
+// operand fragments from global memory, one step of 4 ahead.  Every output is accumulated over b in
+// increasing steps of 4 in every variant (steps past n1 add zero products), so all of them give
+// the same values.
+typedef double d4v __attribute__((ext_vector_type(4)));
+// operand and result layouts of v_mfma_f64_16x16x4f64 for lane l: A[l % 16][l / 16],
+// B[l / 16][l % 16], element r of D: D[l / 16 + 4 r][l % 16]
+__device__ __forceinline__ d4v mfma_f64(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// The same transform with both operands staged through LDS (`stage`: kStageDoubles): output tiles
-// of 128 x TX (TX = 64 with 512 threads, 128 with 1024), a 4 x 4 block per thread, the contraction in
-// chunks of 8 whose W and input slices every thread reads from LDS.  The global loads of a chunk are
-// shared by the whole tile, instead of each thread streaming its own W rows and input columns.
-template <int NT, bool TRANS>
-__device__ __forceinline__ void coarse_transform_lds(int n1, const G<double>* __restrict__ V, const double* in,
-                                                     double* out, double* stage) {
-  constexpr int TA = 128, TX = NT / 8, KC = 8;
-  static_assert((TA / 4) * (TX / 4) == NT && KC * (TA + TX) <= kStageDoubles, "tile shape");
+template <bool WT>
+__device__ __forceinline__ double w_at(const G<double>* __restrict__ V, int n1, int a, int b) {
+  return (a < n1 && b < n1) ? (WT ? V[b * n1 + a] : V[a * n1 + b]) : 0.0;
+}
+template <bool IT>
+__device__ __forceinline__ double in_at(const double* in, int n1, int b, int x) {
+  return (b < n1 && x < n1) ? (IT ? in[x * n1 + b] : in[b * n1 + x]) : 0.0;
+}
+
+template <int NT, int BC, bool WT, bool IT, bool OT>
+__device__ void coarse_gemm(int n1, const G<double>* __restrict__ V, const double* in, double* out, double* stage) {
+  constexpr int NW = NT / 64, WC = NW / 4, TA = 128, TX = WC * 16 * BC, KC = 8;
+  static_assert(NW % 4 == 0 && KC * (TA + TX) <= kStageDoubles, "tile shape");
+  // the next chunk is held in registers only in the builds with the full register budget (BC = 4)
+  constexpr bool PF = BC >= 4;
+  constexpr int EW = PF ? KC * TA / NT : 1, EI = PF ? KC * TX / NT : 1;  // chunk elements per thread
+  static_assert(!PF || (EW * NT == KC * TA && EI * NT == KC * TX), "chunk split");
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wr = wv % 4, wc = wv / 4, li = lane & 15, lk = lane >> 4;
   L3<double>* ws = (L3<double>*)stage;  // [KC][TA]
-  L3<double>* vs = ws + KC * TA;        // [KC][TX]
-  const int ta = threadIdx.x / (TX / 4), tx = threadIdx.x % (TX / 4);
+  L3<double>* is = ws + KC * TA;        // [KC][TX]
   for (int a0 = 0; a0 < n1; a0 += TA)
     for (int x0 = 0; x0 < n1; x0 += TX) {
-      double acc[4][4] = {};
-      for (int k0 = 0; k0 < n1; k0 += KC) {
-        __syncthreads();  // the previous chunk has been consumed
-        for (int e = threadIdx.x; e < KC * TA; e += NT) {
-          // consecutive threads take consecutive columns of V in both layouts
-          const int kk = TRANS ? e / TA : e % KC, aa = TRANS ? e % TA : e / KC;
-          const int b = k0 + kk, a = a0 + aa;
-          ws[kk * TA + aa] = (b < n1 && a < n1) ? (TRANS ? V[b * n1 + a] : V[a * n1 + b]) : 0.0;
-        }
-        for (int e = threadIdx.x; e < KC * TX; e += NT) {
-          const int kk = e / TX, xx = e % TX;
-          const int b = k0 + kk, x = x0 + xx;
-          vs[e] = (b < n1 && x < n1) ? in[b * n1 + x] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int kk = 0; kk < KC; ++kk) {
-          double w[4], v[4];
+      d4v acc[2][BC];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            w[u] = ws[kk * TA + ta * 4 + u];
-            v[u] = vs[kk * TX + tx * 4 + u];
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < BC; ++cb) acc[rb][cb] = d4v{0.0, 0.0, 0.0, 0.0};
+      const int ra = a0 + wr * 32 + li, cx = x0 + wc * 16 * BC + li;
+      if (stage) {
+        // element e of a chunk: W part kk = e / TA, aa = e % TA (WT: consecutive a are consecutive in
+        // memory) or kk = e % KC, aa = e / KC; In part likewise with IT
+        double pw[EW], pi[EI];
+        auto fetch = [&](int k0) {
+#pragma unroll
+          for (int j = 0; j < EW; ++j) {
+            const int e = threadIdx.x + j * NT;
+            const int kk = WT ? e / TA : e % KC, aa = WT ? e % TA : e / KC;
+            pw[j] = w_at<WT>(V, n1, a0 + aa, k0 + kk);
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
+          for (int j = 0; j < EI; ++j) {
+            const int e = threadIdx.x + j * NT;
+            const int kk = IT ? e % KC : e / TX, xx = IT ? e / KC : e % TX;
+            pi[j] = in_at<IT>(in, n1, k0 + kk, x0 + xx);
+          }
+        };
+        if constexpr (PF) fetch(0);
+        for (int k0 = 0; k0 < n1; k0 += KC) {
+          __syncthreads();  // the previous chunk has been consumed
+          if constexpr (PF) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[u][q] += w[u] * v[q];
+            for (int j = 0; j < EW; ++j) {
+              const int e = threadIdx.x + j * NT;
+              const int kk = WT ? e / TA : e % KC, aa = WT ? e % TA : e / KC;
+              ws[kk * TA + aa] = pw[j];
+            }
+#pragma unroll
+            for (int j = 0; j < EI; ++j) {
+              const int e = threadIdx.x + j * NT;
+              const int kk = IT ? e % KC : e / TX, xx = IT ? e / KC : e % TX;
+              is[kk * TX + xx] = pi[j];
+            }
+          } else {
+            for (int e = threadIdx.x; e < KC * TA; e += NT) {
+              const int kk = WT ? e / TA : e % KC, aa = WT ? e % TA : e / KC;
+              ws[kk * TA + aa] = w_at<WT>(V, n1, a0 + aa, k0 + kk);
+            }
+            for (int e = threadIdx.x; e < KC * TX; e += NT) {
+              const int kk = IT ? e % KC : e / TX, xx = IT ? e / KC : e % TX;
+              is[kk * TX + xx] = in_at<IT>(in, n1, k0 + kk, x0 + xx);
+            }
+          }
+          __syncthreads();
+          if constexpr (PF)
+            if (k0 + KC < n1) fetch(k0 + KC);
+#pragma unroll
+          for (int ks = 0; ks < KC; ks += 4) {
+            double fa[2], fb[BC];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) fa[rb] = ws[(ks + lk) * TA + wr * 32 + rb * 16 + li];
+#pragma unroll
+            for (int cb = 0; cb < BC; ++cb) fb[cb] = is[(ks + lk) * TX + wc * 16 * BC + cb * 16 + li];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+              for (int cb = 0; cb < BC; ++cb) acc[rb][cb] = mfma_f64(fa[rb], fb[cb], acc[rb][cb]);
+          }
+        }
+      } else {
+        double fa[2], fb[BC];
+        auto frag = [&](int k0) {
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb) fa[rb] = w_at<WT>(V, n1, ra + rb * 16, k0 + lk);
+#pragma unroll
+          for (int cb = 0; cb < BC; ++cb) fb[cb] = in_at<IT>(in, n1, k0 + lk, cx + cb * 16);
+        };
+        frag(0);
+        for (int k0 = 0; k0 < n1; k0 += 4) {
+          const double ca0 = fa[0], ca1 = fa[1];
+          double cbv[BC];
+#pragma unroll
+          for (int cb = 0; cb < BC; ++cb) cbv[cb] = fb[cb];
+          if (k0 + 4 < n1) frag(k0 + 4);
+#pragma unroll
+          for (int cb = 0; cb < BC; ++cb) {
+            acc[0][cb] = mfma_f64(ca0, cbv[cb], acc[0][cb]);
+            acc[1][cb] = mfma_f64(ca1, cbv[cb], acc[1][cb]);
+          }
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int a = a0 + ta * 4 + u, x = x0 + tx * 4 + q;
-          if (a < n1 && x < n1) out[a * n1 + x] = acc[u][q];
-        }
+        for (int cb = 0; cb < BC; ++cb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int a = a0 + wr * 32 + rb * 16 + lk + 4 * r, x = x0 + wc * 16 * BC + cb * 16 + li;
+            if (a < n1 && x < n1) out[OT ? x * n1 + a : a * n1 + x] = acc[rb][cb][r];
+          }
     }
 }
 
-// (G + c lam_k H) solves of one n1 x n1 grid by fast diagonalisation with eigenvectors V and the
-// Thomas data tl / tdinv of the modes: c1 in / out, c2 temporary; stage: an LDS staging area of
-// kStageDoubles for the transforms (null: the transforms read their operands directly)
-template <int NT>
+// (G + c lam_k H) solves of one n1 x n1 grid by fast diagonalisation with eigenvectors V (n1 x n1,
+// V[iy][k]) and the Thomas data tl / tdinv of the modes, stored by node (tl[i * n1 + k]): c1 in / out,
+// c2 temporary (the modes' values, node-major: c2[ix * n1 + k]); stage: an LDS staging area of
+// kStageDoubles for the transforms (null: none).  BC: the transforms' wave tile width in blocks.
+template <int NT, int BC = 2>
 __device__ __forceinline__ void fdm_solve(int n1, const double* Vp, const double* tlp, const double* tdp, double* c1,
                                           double* c2, double* stage = nullptr) {
   const G<double>* __restrict__ V = gp(Vp);
-  if (stage)
-    coarse_transform_lds<NT, true>(n1, V, c1, c2, stage);
-  else
-    coarse_transform<NT, true>(n1, V, c1, c2);  // c2[k][ix] = sum_iy V[iy][k] c1[iy][ix]
+  // c2[ix][k] = sum_iy V[iy][k] c1[iy][ix]
+  coarse_gemm<NT, BC, true, false, true>(n1, V, c1, c2, stage);
   __syncthreads();
+  // one thread per mode k, the nodes in sequence; consecutive threads read consecutive words.  The
+  // coefficients and values are loaded 8 nodes at a time, ahead of the recurrence, so their latency
+  // is paid once per chunk; results are stored after the chunk
   for (int k = threadIdx.x; k < n1; k += NT) {
-    // the coefficients and the row values are loaded 8 at a time, ahead of the recurrence, so their
-    // latency is paid once per chunk, not per step; results are stored after the chunk
     constexpr int CH = 8;
-    double* rw = c2 + k * n1;
-    const G<double>* __restrict__ tl = gp(tlp) + k * n1;
-    const G<double>* __restrict__ td = gp(tdp) + k * n1;
+    const G<double>* __restrict__ tl = gp(tlp);
+    const G<double>* __restrict__ td = gp(tdp);
     double yp = 0.0;
     for (int i0 = 0; i0 < n1; i0 += CH) {
       double a[CH], b[CH], v[CH];
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         const int i = i0 + u < n1 ? i0 + u : n1 - 1;
-        a[u] = tl[i];
-        b[u] = td[i];
-        v[u] = rw[i];
+        a[u] = tl[i * n1 + k];
+        b[u] = td[i * n1 + k];
+        v[u] = c2[i * n1 + k];
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
@@ -1067,7 +1099,7 @@ __device__ __forceinline__ void fdm_solve(int n1, const double* Vp, const double
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u)
-        if (i0 + u < n1) rw[i0 + u] = v[u];
+        if (i0 + u < n1) c2[(i0 + u) * n1 + k] = v[u];
     }
     double xn = 0.0;
     for (int i1 = n1 - 1; i1 >= 0; i1 -= CH) {
@@ -1075,8 +1107,8 @@ __device__ __forceinline__ void fdm_solve(int n1, const double* Vp, const double
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         const int i = i1 - u + 1;  // multiplier l_{i+1} for row i = i1 - u
-        a[u] = (i >= 1 && i < n1) ? tl[i] : 0.0;
-        v[u] = rw[i1 - u >= 0 ? i1 - u : 0];
+        a[u] = (i >= 1 && i < n1) ? tl[i * n1 + k] : 0.0;
+        v[u] = c2[(i1 - u >= 0 ? i1 - u : 0) * n1 + k];
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
@@ -1088,23 +1120,20 @@ __device__ __forceinline__ void fdm_solve(int n1, const double* Vp, const double
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u)
-        if (i1 - u >= 0) rw[i1 - u] = v[u];
+        if (i1 - u >= 0) c2[(i1 - u) * n1 + k] = v[u];
     }
   }
   __syncthreads();
-  if (stage)
-    coarse_transform_lds<NT, false>(n1, V, c2, c1, stage);
-  else
-    coarse_transform<NT, false>(n1, V, c2, c1);  // c1[iy][ix] = sum_k V[iy][k] c2[k][ix]
+  // c1[iy][ix] = sum_k V[iy][k] c2[ix][k]
+  coarse_gemm<NT, BC, false, true, false>(n1, V, c2, c1, stage);
   __syncthreads();
 }
 
-// exact p = 1 solve of A_{h,1} = M1 + c K1 (c1 in / out, c2 temporary); the LDS-staged transforms
-// only from n1 = 128 up (at smaller sizes the direct ones have fewer dependent steps)
-template <int NT>
+// exact p = 1 solve of A_{h,1} = M1 + c K1 (c1 in / out, c2 temporary)
+template <int NT, int BC>
 __device__ __forceinline__ void coarse_solve(const InstDev& I, const LevelDev& L, double* c1, double* c2,
                                              double* stage) {
-  fdm_solve<NT>(I.n1, I.V, L.tl, L.tdinv, c1, c2, I.n1 >= kStageMinN1 ? stage : nullptr);
+  fdm_solve<NT, BC>(I.n1, I.V, L.tl, L.tdinv, c1, c2, stage);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1329,10 +1358,10 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
     for (int i = threadIdx.x; i < I.ndof1; i += NT) c1[i] = c2[i];
     __syncthreads();
   } else {
-    coarse_solve<NT>(I, L, c1, c2, stage);
+    coarse_solve<NT, Build<OCC>::GBC>(I, L, c1, c2, stage);
     // the staging area may overlap the triangular solves' window: restore its zero word, which the
     // solves read for padding entries (FP64 data left there can read as a NaN in FP32)
-    if (stage && I.n1 >= kStageMinN1 && win && threadIdx.x == 0) win[zwin] = (VT)0;
+    if (stage && win && threadIdx.x == 0) win[zwin] = (VT)0;
   }
   // step 4: prolongation and update d += (Mp^L)^{-1} P e1
   if constexpr (!ST) {
@@ -1429,8 +1458,8 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
   // window of the triangular solves when y is in global memory; its zero word likewise
   VT* win = (!(MASK & kY) && plan.off_win >= 0) ? (VT*)(smem + plan.off_win) : nullptr;
   // LDS staging area of the p = 1 transforms (it may share the window's bytes: the two are never in
-  // use at once); the builds limited to 128 registers keep the direct transforms
-  double* stage = (plan.off_stage >= 0 && (OCC == 1 || OCC == 4)) ? (double*)(smem + plan.off_stage) : nullptr;
+  // use at once)
+  double* stage = plan.off_stage >= 0 ? (double*)(smem + plan.off_stage) : nullptr;
   if (win && threadIdx.x == 0) win[plan.zwin] = (VT)0;
   // LDS staging area of the band passes when y is in global memory
   Stg bst;
