@@ -668,7 +668,8 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
     // bc = values per lane.  The kernel's lane g of TG per row reads 16-byte units g, g + TG, ...
     const int R = std::max(1, S.max_rows), AS = RW, TGh = TG;
     const int V = H->fp32 ? 4 : 2;  // values per 16 bytes
-    const size_t nslots = (size_t)(S.nlev + 2) * R + 1;
+    // records past the last level are empty (the window mode's slab solve reads up to nlev + 2)
+    const size_t nslots = (size_t)(S.nlev + 3) * R + 1;
     std::vector<Meta4> meta(nslots, Meta4{-1, 0, 0, 0});
     std::vector<int> acol(aslots, 0);  // columns relative to the zero word zidx (padding: 0)
     std::vector<double> aval(aslots, 0.0);
@@ -692,6 +693,51 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
           acol[(1 + sl) * AS + t] = colmap(S.oci[S.orp[q] + t]) - zidx;
         }
       }
+    // FP32 window mode, 512 threads of 4 lanes per row: slab tables when a level's dense rows fit
+    // kDch chunks and the window columns 16 bits
+    T.dch = 0;
+    T.lsv = 0;
+    T.acol16 = nullptr;
+    if (T.winW > 0 && H->fp32 && TGh == 4 && R * TGh == 512 && AS % TGh == 0) {
+      size_t maxlev = 0;
+      for (int l = 0; l < S.nlev; ++l) {
+        size_t sum = 0;
+        for (int q = S.lev_ptr[l]; q < S.lev_ptr[l + 1]; ++q) sum += (size_t)TGh * (meta[1 + (size_t)l * R + (q - S.lev_ptr[l])].bqc >> 16);
+        maxlev = std::max(maxlev, sum);
+      }
+      const int dch = (int)((maxlev * 4 + kChunkBytes - 1) / kChunkBytes);
+      bool c16 = true;
+      for (int c : acol) c16 = c16 && c >= -32768 && c <= 32767;
+      const int lsv = std::max(1, dch) * (kChunkBytes / 4);
+      const size_t slab_vals = (size_t)kSlab0 + (size_t)S.nlev * lsv;
+      if (dch >= 1 && dch <= kDch && c16 && slab_vals * sizeof(double) < (size_t)kBufBytes) {
+        std::vector<double> slab(slab_vals, 0.0);
+        for (int l = 0; l < S.nlev; ++l) {
+          size_t at = (size_t)kSlab0 + (size_t)l * lsv;
+          for (int q = S.lev_ptr[l]; q < S.lev_ptr[l + 1]; ++q) {
+            Meta4& m = meta[1 + (size_t)l * R + (q - S.lev_ptr[l])];
+            const size_t len = (size_t)TGh * (m.bqc >> 16);
+            std::copy(dfast.begin() + m.bo, dfast.begin() + m.bo + len, slab.begin() + at);
+            m.bo = (int)at;
+            at += len;
+          }
+        }
+        dfast.swap(slab);
+        // 16-bit columns, lane-major: entry (k * TG + g) * WA + e of a row at g * KA + k * WA + e
+        const int KA = AS / TGh, WA = std::min(KA, V);
+        std::vector<short> a16(acol.size(), 0);
+        for (size_t sl = 0; sl + 1 < acol.size() / AS; ++sl)
+          for (int t = 0; t < AS; ++t) {
+            const int k = t / WA / TGh, g = t / WA % TGh, e = t % WA;
+            a16[(1 + sl) * AS + g * KA + k * WA + e] = (short)acol[(1 + sl) * AS + t];
+          }
+        short* p16;
+        TRY(upload_vec(H, a16, &p16));
+        T.acol16 = p16;
+        T.dch = dch;
+        T.lsv = lsv;
+      }
+    }
     T.R = R;
     T.AS = AS;
     Meta4* m4;

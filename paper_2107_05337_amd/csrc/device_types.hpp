@@ -23,6 +23,11 @@ constexpr int kSbufWords = 320;
 // LDS staging area of the exact p = 1 solve's dense transforms (doubles)
 constexpr int kStageDoubles = 2048;
 constexpr int kBandStageMin = 16 * 1024;  // smallest LDS staging area of the band passes (bytes)
+// slab tables of the window-mode triangular solves: 8 KB chunks (one 16-byte load per lane of a
+// 512-thread workgroup), at most kDch per level, the first slab at value kSlab0 of dfast
+constexpr int kChunkBytes = 8192;
+constexpr int kDch = 5;
+constexpr int kSlab0 = kChunkBytes / 4;
 // LDS per workgroup of gfx950 (160 KiB)
 constexpr int kLdsBytes = 160 * 1024;
 // default row-block size of the triangular solves
@@ -53,6 +58,12 @@ struct TriDev {
   const void* aval;              // [(1 + nlev * R) * AS] off-block values, row 0 = padding
   const int* acol;               // [(1 + nlev * R) * AS] off-block columns minus the zero word's
                                  // index (padding: 0, i.e. the zero word)
+  // FP32 window-mode slab tables (dch > 0): level l's dense rows lie contiguous, in row-slot order,
+  // in dfast[kSlab0 + l * lsv, + lsv) (lsv = dch x kChunkBytes / 4 values; Meta4::bo stays absolute),
+  // and acol16 holds the off-block columns as 16-bit values, lane g's KA of them contiguous at
+  // (1 + l * R + r) * AS + g * KA
+  int dch, lsv;
+  const short* acol16;
   // general path: level-ordered CSR
   const int* lev_ptr;
   const int* row;

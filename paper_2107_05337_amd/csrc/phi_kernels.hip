@@ -846,6 +846,157 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
   }
 }
 
+
+// FP32 window-mode solve over slab tables (TriDev::dch > 0; 512 threads, 4 lanes per row, 128 row slots).
+// A level's dense rows lie contiguous in a slab of dch x 8 KB, which the whole workgroup copies into
+// the LDS area dst with one 16-byte load per lane per 8 KB, so the dense rows cost no loads for their
+// padding lanes; the off-block columns are 16 bits, each lane's KA of them contiguous.  A level of
+// the window mode is bound by the CU's vector-memory path (instructions, padding lanes included, and
+// bytes), so these take about a third fewer instructions.  The off-block rows are requested one level
+// ahead, the right-hand sides and slabs two levels ahead (two register sets, even and odd levels),
+// the metadata three.  The arithmetic is trsv_fast's, in the same order.
+template <int KA>
+__device__ __noinline__ void trsv_slab(const TriDev* __restrict__ Tp, int zidx, const float* in_g, L3<float>* y,
+                                       L3<float>* sbuf, float* yg, L3<float>* dst) {
+  typedef float VT;
+  constexpr int TG = 4, RW = KA * TG, V = 4, WA = KA < V ? KA : V, NU = KA / WA, CB = KA * 2;
+  constexpr int BCM = (kDenseWin + V - 1 + TG * V - 1) / (TG * V) * V, ND = BCM / V;
+  static_assert(kRowSlots - 1 + TG * BCM <= kSbufWords, "sbuf too small for the dense rows");
+  typedef VT VV __attribute__((ext_vector_type(4)));
+  typedef unsigned U4 __attribute__((ext_vector_type(4)));
+  Tp = uniform_ptr(Tp);
+  const __amdgpu_buffer_rsrc_t rval = table_rsrc(Tp->aval), rc16 = table_rsrc(Tp->acol16),
+                               rden = table_rsrc(Tp->dfast), rmeta = table_rsrc(Tp->meta), rin = table_rsrc(in_g);
+  const int R = __builtin_amdgcn_readfirstlane(Tp->R), nlev = __builtin_amdgcn_readfirstlane(Tp->nlev);
+  const int dch = __builtin_amdgcn_readfirstlane(Tp->dch), lsv = __builtin_amdgcn_readfirstlane(Tp->lsv);
+  const int winW = __builtin_amdgcn_readfirstlane(Tp->winW), winN = __builtin_amdgcn_readfirstlane(Tp->winN);
+  const int r = threadIdx.x / TG, g = threadIdx.x & (TG - 1);
+  const L3<VT>* yz = y + __builtin_amdgcn_readfirstlane(zidx);
+  auto load_meta = [&](int l, Meta4& m) {
+    unsigned u[4];
+    buf_load<16>(rmeta, g == 0 ? (1 + l * R + r) * 16 : kOff, u);
+    m = Meta4{(int)u[0], (int)u[1], (int)u[2], (int)u[3]};
+  };
+  auto bcast = [&](Meta4& m) {
+    m.row = __builtin_amdgcn_mov_dpp(m.row, 0x00, 0xF, 0xF, true);  // quad_perm [0, 0, 0, 0]
+    m.bo = __builtin_amdgcn_mov_dpp(m.bo, 0x00, 0xF, 0xF, true);
+    m.bqc = __builtin_amdgcn_mov_dpp(m.bqc, 0x00, 0xF, 0xF, true);
+    m.na = __builtin_amdgcn_mov_dpp(m.na, 0x00, 0xF, 0xF, true);
+  };
+  auto load_a = [&](int l, const Meta4& m, VT* av, int* ac) {
+    const int base = RW + (l * R + r) * RW;
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+      const int e0 = (k * TG + g) * WA;
+      unsigned uv[WA];
+      buf_load<WA * 4>(rval, e0 < m.na ? (base + e0) * 4 : kOff, uv);
+#pragma unroll
+      for (int e = 0; e < WA; ++e) av[k * WA + e] = __builtin_bit_cast(float, uv[e]);
+    }
+    // lane g's columns (k * WA + e order) at (base + g * KA) * 2 bytes, zero past the row's entries
+    const bool live = l < nlev;
+    const int c0 = (base + g * KA) * 2;
+    unsigned uc[(CB + 3) / 4];
+#pragma unroll
+    for (int q = 0; q < CB / 16; ++q) buf_load<16>(rc16, live ? c0 + q * 16 : kOff, uc + q * 4);
+    if constexpr (CB % 16 != 0) buf_load<CB % 16>(rc16, live ? c0 + CB / 16 * 16 : kOff, uc + CB / 16 * 4);
+#pragma unroll
+    for (int j = 0; j < KA; ++j) ac[j] = (int)(short)(unsigned short)(uc[j / 2] >> (16 * (j % 2)));
+  };
+  // the row's right-hand side, by the lane that writes its result (it holds the raw record)
+  auto load_x = [&](const Meta4& m, VT& xin) {
+    unsigned u[1];
+    buf_load<4>(rin, g == 0 && m.row >= 0 ? m.row * 4 : kOff, u);
+    xin = __builtin_bit_cast(float, u[0]);
+  };
+  auto load_d = [&](int l, U4* dr) {
+    const int b0 = (kSlab0 + l * lsv) * 4 + (int)threadIdx.x * 16;
+    const bool live = l < nlev;
+#pragma unroll
+    for (int c = 0; c < kDch; ++c) {
+      unsigned u[4];
+      buf_load<16>(rden, live && c < dch ? b0 + c * kChunkBytes : kOff, u);
+      dr[c] = U4{u[0], u[1], u[2], u[3]};
+    }
+  };
+  auto store_d = [&](const U4* dr) {
+#pragma unroll
+    for (int c = 0; c < kDch; ++c) ((L3<U4>*)dst)[c * (kChunkBytes / 16) + threadIdx.x] = dr[c];
+  };
+  auto phase_a = [&](const VT* av, const int* ac, int row, VT xin) {
+    VT s = 0;
+#pragma unroll
+    for (int j = 0; j < KA; ++j) s += av[j] * yz[ac[j]];
+    s = row_sum<TG>(s);
+    if (g == 0 && row >= 0) sbuf[r] = xin - s;
+  };
+  auto phase_b = [&](const Meta4& m, int l) {
+    VT s = 0;
+    const L3<VV>* sp = (const L3<VV>*)(sbuf + (m.bqc & 0xffff));
+    const int rel = m.row >= 0 ? m.bo - (kSlab0 + l * lsv) : 0;  // the row's offset in its slab
+    const L3<VV>* dp = (const L3<VV>*)(dst + rel);
+    const int bc = m.bqc >> 16;
+#pragma unroll 3
+    for (int k = 0; k < ND; ++k) {
+      const VV sv = sp[k * TG + g];
+      const bool on = k * V < bc;
+      const VV dv = dp[on ? k * TG + g : 0];
+#pragma unroll
+      for (int e = 0; e < V; ++e) s += (on ? dv[e] : (VT)0) * sv[e];
+    }
+    s = row_sum<TG>(s);
+    if (g == 0 && m.row >= 0) {
+      const int line = m.row / winN;
+      y[(line % winW) * winN + (m.row - line * winN)] = s;
+      ((G<VT>*)yg)[m.row] = s;
+    }
+  };
+  // level l starts with C and N (levels l and l + 1, broadcast) and N2 (level l + 2, raw), its own
+  // off-block rows, and its right-hand side and slab in register set l mod 2 (level l + 1's in the
+  // other set)
+  VT av[KA], x0, x1;
+  int ac[KA];
+  U4 d0[kDch], d1[kDch];
+  Meta4 C, N, N2;
+  load_meta(0, C);
+  load_meta(1, N);
+  load_meta(2, N2);
+  __builtin_amdgcn_sched_barrier(0);
+  load_x(C, x0);
+  load_x(N, x1);
+  bcast(C);
+  load_a(0, C, av, ac);
+  __builtin_amdgcn_sched_barrier(0);
+  load_d(0, d0);
+  load_d(1, d1);
+  __builtin_amdgcn_sched_barrier(0);
+  // one level: phase A, its slab into LDS, level l + 1's off-block rows requested, phase B from LDS,
+  // then level l + 3's metadata and level l + 2's right-hand side and slab
+  auto level = [&](int l, VT& xin, U4* dr) {
+    phase_a(av, ac, C.row, xin);
+    store_d(dr);
+    __builtin_amdgcn_sched_barrier(0);
+    bcast(N);
+    load_a(l + 1, N, av, ac);
+    lds_barrier();
+    phase_b(C, l);
+    __builtin_amdgcn_sched_barrier(0);
+    Meta4 N3;
+    load_meta(l + 3, N3);
+    load_x(N2, xin);
+    load_d(l + 2, dr);
+    C = N;
+    N = N2;
+    N2 = N3;
+    lds_barrier();
+  };
+  for (int l = 0; l < nlev; l += 2) {
+    level(l, x0, d0);
+    if (l + 1 >= nlev) break;
+    level(l + 1, x1, d1);
+  }
+}
+
 // General path (any schedule, y in LDS or global): same two phases with loops, full barriers.
 template <typename VT, int NT>
 __device__ void trsv_general(const TriDev& T, const VT* in, VT* y, VT* sbuf) {
@@ -886,7 +1037,7 @@ __device__ void trsv_general(const TriDev& T, const VT* in, VT* y, VT* sbuf) {
 // win: the LDS window of the triangular solves when y is in global memory (null: none)
 template <typename VT, bool YLDS, bool IN_GLOBAL, int OCC>
 __device__ __forceinline__ void trsv(const TriDev& T, int ka, int zidx, const VT* in, VT* y, VT* sbuf, VT* win,
-                                     int zwin) {
+                                     int zwin, Stg st = Stg{}) {
   L3<VT>* sl = (L3<VT>*)sbuf;
   if (YLDS && T.fast) {
     L3<VT>* yl = (L3<VT>*)y;
@@ -902,16 +1053,40 @@ __device__ __forceinline__ void trsv(const TriDev& T, int ka, int zidx, const VT
       trsv_fast<VT, IN_GLOBAL, 16, OCC, false>(&T, zidx, in, yl, sl, nullptr);
   } else if (!YLDS && IN_GLOBAL && (OCC == 1 || OCC == 2) && win && T.fast && T.winW > 0) {
     L3<VT>* wl = (L3<VT>*)win;
-    if (ka <= 2)
-      trsv_fast<VT, true, 2, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
-    else if (ka <= 4)
-      trsv_fast<VT, true, 4, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
-    else if (ka <= 8)
-      trsv_fast<VT, true, 8, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
-    else if (ka <= 12)
-      trsv_fast<VT, true, 12, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
-    else
-      trsv_fast<VT, true, 16, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
+    bool slab = false;
+    if constexpr (sizeof(VT) == 4 && OCC == 1) {
+      // slab tables, with the band-pass staging area as the slabs' LDS area
+      if (T.dch > 0 && T.R * 4 == Build<OCC>::NT && st.p && st.bytes >= kDch * kChunkBytes) {
+        slab = true;
+        const float* inf = (const float*)in;
+        L3<float>* wf = (L3<float>*)win;
+        L3<float>* sf = (L3<float>*)sbuf;
+        float* yf = (float*)y;
+        L3<float>* ds = (L3<float>*)st.p;
+        if (ka <= 2)
+          trsv_slab<2>(&T, zwin, inf, wf, sf, yf, ds);
+        else if (ka <= 4)
+          trsv_slab<4>(&T, zwin, inf, wf, sf, yf, ds);
+        else if (ka <= 8)
+          trsv_slab<8>(&T, zwin, inf, wf, sf, yf, ds);
+        else if (ka <= 12)
+          trsv_slab<12>(&T, zwin, inf, wf, sf, yf, ds);
+        else
+          trsv_slab<16>(&T, zwin, inf, wf, sf, yf, ds);
+      }
+    }
+    if (!slab) {
+      if (ka <= 2)
+        trsv_fast<VT, true, 2, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
+      else if (ka <= 4)
+        trsv_fast<VT, true, 4, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
+      else if (ka <= 8)
+        trsv_fast<VT, true, 8, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
+      else if (ka <= 12)
+        trsv_fast<VT, true, 12, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
+      else
+        trsv_fast<VT, true, 16, OCC, true, kWinDense<VT>>(&T, zwin, in, wl, sl, y);
+    }
   } else {
     trsv_general<VT, Build<OCC>::NT>(T, in, y, sbuf);
   }
@@ -1327,14 +1502,14 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
   const TriDev& TL = Build<OCC>::TG == 8 ? L.L8 : L.L;
   const TriDev& TU = Build<OCC>::TG == 8 ? L.U8 : L.U;
   // step 1: pre-smoothing d = S r, then nu1 - 1 further steps d += S (r - A d)
-  trsv<VT, YL, true, OCC>(TL, ka, zidx, r, y, sbuf, win, zwin);
-  trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf, win, zwin);
+  trsv<VT, YL, true, OCC>(TL, ka, zidx, r, y, sbuf, win, zwin, bst);
+  trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf, win, zwin, bst);
   for (int i = threadIdx.x; i < n; i += NT) d[i] = y[i];
   __syncthreads();
   for (int m = 1; m < nu1; ++m) {
     resid();
-    trsv<VT, YL, !(MASK & kS), OCC>(TL, ka, zidx, s, y, sbuf, win, zwin);
-    trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf, win, zwin);
+    trsv<VT, YL, !(MASK & kS), OCC>(TL, ka, zidx, s, y, sbuf, win, zwin, bst);
+    trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf, win, zwin, bst);
     for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
     __syncthreads();
   }
@@ -1377,8 +1552,8 @@ __device__ void vcycle(const InstDev& I, const LevelDev& L, int nu1, int nu2, co
   // step 5: nu2 post-smoothing steps d += S (r - A d)
   for (int m = 0; m < nu2; ++m) {
     resid();
-    trsv<VT, YL, !(MASK & kS), OCC>(TL, ka, zidx, s, y, sbuf, win, zwin);
-    trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf, win, zwin);
+    trsv<VT, YL, !(MASK & kS), OCC>(TL, ka, zidx, s, y, sbuf, win, zwin, bst);
+    trsv<VT, YL, !YL, OCC>(TU, ka, zidx, y, y, sbuf, win, zwin, bst);
     for (int i = threadIdx.x; i < n; i += NT) d[i] += y[i];
     __syncthreads();
   }
