@@ -275,19 +275,27 @@ struct Staged {
 
 __device__ __forceinline__ int al16(int b) { return (b + 15) / 16 * 16; }
 
+// copies n elements of src into dst (and of src2 into dst2 when given), kCopyU loads of each in
+// flight per thread before the first store
+constexpr int kCopyU = 16;
 template <int NT, typename T, typename S>
-__device__ __forceinline__ void stage_copy(L3<T>* dst, const S* src, int n) {
-  for (int e0 = threadIdx.x; e0 < n; e0 += kStU * NT) {
-    T v[kStU];
+__device__ __forceinline__ void stage_copy(L3<T>* dst, const S* src, int n, L3<T>* dst2 = nullptr,
+                                           const S* src2 = nullptr) {
+  for (int e0 = threadIdx.x; e0 < n; e0 += kCopyU * NT) {
+    T v[kCopyU], v2[kCopyU];
 #pragma unroll
-    for (int u = 0; u < kStU; ++u) {
+    for (int u = 0; u < kCopyU; ++u) {
       const int e = e0 + u * NT;
       v[u] = e < n ? (T)src[e] : (T)0;
+      if (src2) v2[u] = e < n ? (T)src2[e] : (T)0;
     }
 #pragma unroll
-    for (int u = 0; u < kStU; ++u) {
+    for (int u = 0; u < kCopyU; ++u) {
       const int e = e0 + u * NT;
-      if (e < n) dst[e] = v[u];
+      if (e < n) {
+        dst[e] = v[u];
+        if (src2) dst2[e] = v2[u];
+      }
     }
   }
 }
@@ -414,8 +422,7 @@ __device__ void pass_x2_st(int nrows, int nin, const BandDev& B1d, const BandDev
   L3<AT>* b2 = (L3<AT>*)(st.p + bw);
   L3<IT>* rows = (L3<IT>*)(st.p + 2 * bw);
   __syncthreads();
-  stage_copy<NT>(b1, band_ptr<AT>(B1d), nout * w);
-  stage_copy<NT>(b2, band_ptr<AT>(B2d), nout * w);
+  stage_copy<NT>(b1, band_ptr<AT>(B1d), nout * w, b2, band_ptr<AT>(B2d));
   for (int r0 = 0; r0 < nrows; r0 += RC) {
     const int rc = min(RC, nrows - r0);
     if (r0 > 0) __syncthreads();
@@ -460,10 +467,8 @@ __device__ double pass_y2_st(int ncols, int nin, const BandDev& B1d, const BandD
     L3<TT>* r1 = (L3<TT>*)(st.p + 2 * bw);
     L3<TT>* r2 = (L3<TT>*)(st.p + 2 * bw + al16(nr * rowb));
     if (o0 > 0) __syncthreads();
-    stage_copy<NT>(c1, B1 + (int64_t)o0 * w, rc * w);
-    stage_copy<NT>(c2, B2 + (int64_t)o0 * w, rc * w);
-    stage_copy<NT>(r1, T1 + (int64_t)jlo * ncols, nr * ncols);
-    stage_copy<NT>(r2, T2 + (int64_t)jlo * ncols, nr * ncols);
+    stage_copy<NT>(c1, B1 + (int64_t)o0 * w, rc * w, c2, B2 + (int64_t)o0 * w);
+    stage_copy<NT>(r1, T1 + (int64_t)jlo * ncols, nr * ncols, r2, T2 + (int64_t)jlo * ncols);
     __syncthreads();
     const int base = o0 * ncols, tot = rc * ncols;
     for (int t0 = own_from<NT>(base); t0 < tot; t0 += kStU * NT) {
