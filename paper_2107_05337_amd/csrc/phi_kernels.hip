@@ -255,13 +255,12 @@ __device__ __forceinline__ double pass_y2(int ncols, int nin, const BandDev& B1d
 }
 
 // LDS staging of the band passes whose vectors are in global memory (y not in LDS): per chunk of
-// rows the band entries and the input rows are copied into LDS by every thread, kStU loads in
+// rows the band entries and the input rows are copied into LDS by every thread, many loads in
 // flight per thread, and the outputs are formed from LDS.  The direct passes pay one global
 // load latency per output row and thread in sequence; here a chunk costs a few.  Each output is
-// summed in the same order and with the same operations as in the direct passes, and each
-// thread forms the same outputs (index = thread mod NT), so results agree bitwise.  p = null,
-// or an area too small for the pass: the direct pass.  Vectors are read through generic
-// pointers (any of them may be in LDS).
+// summed in the same order and with the same operations as in the direct passes, so the outputs
+// agree bitwise.  p = null, or an area too small for the pass: the direct pass.  Vectors are read
+// through generic pointers (any of them may be in LDS).
 struct Stg {
   unsigned char* p = nullptr;
   int bytes = 0;
@@ -306,11 +305,77 @@ __device__ __forceinline__ int own_from(int base) {
   return ((int)threadIdx.x - base % NT + NT) % NT;
 }
 
+// Compute of the staged passes with bands of at most kBandMax entries: band rows staged at stride kBS
+// with zeros past w, so every output takes kBandMax taps exactly as the direct passes do (same
+// products, same order: the values agree bitwise).  Register blocking over four outputs:
+// first-direction passes give each thread one output column o of four rows, its band row loaded once;
+// second-direction passes give each thread four consecutive output rows of one column, the
+// 4 + kBandMax - 1 input values they share loaded once.  The norms' partial sums are grouped by thread
+// differently from the direct passes (their roundings may differ in the last place).
+constexpr int kBS = kBandMax + 1;
+
+// band rows o0 .. o0 + n - 1 of B (and B2) into dst (dst2) at stride kBS, zero past w
+template <int NT, typename AT>
+__device__ __forceinline__ void stage_band(L3<AT>* dst, const G<AT>* __restrict__ B, int o0, int n, int w,
+                                           L3<AT>* dst2 = nullptr, const G<AT>* __restrict__ B2 = nullptr) {
+  for (int e = threadIdx.x; e < n * kBS; e += NT) {
+    const int o = e / kBS, d = e - o * kBS;
+    const int64_t src = (int64_t)(o0 + o) * w + d;
+    dst[e] = d < w ? B[src] : (AT)0;
+    if (B2) dst2[e] = d < w ? B2[src] : (AT)0;
+  }
+}
+
+// first-direction outputs of rows [r, r + cnt) of the staged input, column o (one or two bands)
+template <typename AT, typename IT, typename OT, bool TWO>
+__device__ __forceinline__ void x_block(const L3<AT>* b1, const L3<AT>* b2, const L3<IT>* rows, int nin, int lo,
+                                        int o, int r, int cnt, OT* out1, OT* out2, int64_t orow, int nout) {
+  AT c1[kBandMax], c2[kBandMax];
+#pragma unroll
+  for (int d = 0; d < kBandMax; ++d) {
+    c1[d] = b1[o * kBS + d];
+    if (TWO) c2[d] = b2[o * kBS + d];
+  }
+  const bool inner = o + lo >= 0 && o + lo + kBandMax - 1 < nin;
+  int jj[kBandMax];
+#pragma unroll
+  for (int d = 0; d < kBandMax; ++d) {
+    const int j = o + lo + d;
+    jj[d] = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (i < cnt) {
+      const L3<IT>* src = rows + (r + i) * nin;
+      AT s1 = 0, s2 = 0;
+      if (inner) {
+        const L3<IT>* sp = src + o + lo;
+#pragma unroll
+        for (int d = 0; d < kBandMax; ++d) {
+          const AT v = (AT)sp[d];
+          s1 += c1[d] * v;
+          if (TWO) s2 += c2[d] * v;
+        }
+      } else {
+#pragma unroll
+        for (int d = 0; d < kBandMax; ++d) {
+          const AT v = (AT)src[jj[d]];
+          s1 += c1[d] * v;
+          if (TWO) s2 += c2[d] * v;
+        }
+      }
+      out1[(orow + i) * nout + o] = (OT)s1;
+      if (TWO) out2[(orow + i) * nout + o] = (OT)s2;
+    }
+  }
+}
+
 // pass_x with staging (the direct pass when one input row and the band do not fit)
 template <int NT, typename AT, typename IT, typename OT>
 __device__ void pass_x_st(int nrows, int nin, const BandDev& Bd, const IT* in, OT* out, Stg st) {
   const int nout = Bd.rows, w = Bd.w, lo = Bd.lo;
-  const int bw = al16(nout * w * (int)sizeof(AT));
+  const bool blk = w <= kBandMax;
+  const int bw = al16(nout * (blk ? kBS : w) * (int)sizeof(AT));
   const int RC = (st.bytes - bw) / (nin * (int)sizeof(IT));
   if (!st.p || RC < 1) {
     pass_x<NT, AT>(nrows, nin, Bd, in, out);
@@ -319,12 +384,24 @@ __device__ void pass_x_st(int nrows, int nin, const BandDev& Bd, const IT* in, O
   L3<AT>* bs = (L3<AT>*)st.p;
   L3<IT>* rows = (L3<IT>*)(st.p + bw);
   __syncthreads();  // earlier readers of the staging area
-  stage_copy<NT>(bs, band_ptr<AT>(Bd), nout * w);
+  if (blk)
+    stage_band<NT, AT>(bs, band_ptr<AT>(Bd), 0, nout, w);
+  else
+    stage_copy<NT>(bs, band_ptr<AT>(Bd), nout * w);
   for (int r0 = 0; r0 < nrows; r0 += RC) {
     const int rc = min(RC, nrows - r0);
     if (r0 > 0) __syncthreads();
     stage_copy<NT>(rows, in + (int64_t)r0 * nin, rc * nin);
     __syncthreads();
+    if (blk) {
+      const int nb = (rc + 3) / 4;
+      for (int t = threadIdx.x; t < nb * nout; t += NT) {
+        const int rb = t / nout, o = t - rb * nout;
+        x_block<AT, IT, OT, false>(bs, bs, rows, nin, lo, o, 4 * rb, min(4, rc - 4 * rb), out, out,
+                                   (int64_t)r0 + 4 * rb, nout);
+      }
+      continue;
+    }
     for (int t = threadIdx.x; t < rc * nout; t += NT) {
       const int rr = t / nout, o = t - rr * nout;
       AT s = 0;
@@ -346,16 +423,39 @@ __device__ __forceinline__ void y_chunk(int o0, int rc, int nin, int lo, int w, 
   jhi = b < 0 ? 0 : (b >= nin ? nin - 1 : b);
 }
 
+// the 4 + kBandMax - 1 staged input values of column c that output rows oA .. oA + 3 reach
+// (clamped to the input, and to the chunk's rows past its last output)
+template <typename AT, typename TT>
+__device__ __forceinline__ void y_column(const L3<TT>* rows, int ncols, int nin, int lo, int jlo, int jhi, int oA,
+                                         int c, AT* v) {
+  const int j0 = oA + lo;
+  if (j0 >= 0 && j0 + 3 + kBandMax - 1 <= jhi) {
+    const L3<TT>* sp = rows + (j0 - jlo) * ncols + c;
+#pragma unroll
+    for (int k = 0; k < 3 + kBandMax; ++k) v[k] = (AT)sp[k * ncols];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3 + kBandMax; ++k) {
+      int j = j0 + k;
+      j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
+      j = j > jhi ? jhi : j;
+      v[k] = (AT)rows[(j - jlo) * ncols + c];
+    }
+  }
+}
+
 // pass_y with staging (the direct pass when w input rows and one band row do not fit)
 template <int NT, typename AT, typename TT, typename ZT, typename OT>
 __device__ double pass_y_st(int ncols, int nin, const BandDev& Bd, const TT* T, AT alpha, const ZT* z, AT beta,
                             bool acc, const double* scy, const double* scx, OT* out, Stg st) {
   const int nout = Bd.rows, w = Bd.w, lo = Bd.lo;
+  const bool blk = w <= kBandMax;
+  const int bstride = blk ? kBS : w;
   const int rowb = ncols * (int)sizeof(TT);
-  const int RC = min(nout, (st.bytes - 16 - (w - 1) * rowb) / (rowb + w * (int)sizeof(AT)));
+  const int RC = min(nout, (st.bytes - 16 - (w - 1) * rowb) / (rowb + bstride * (int)sizeof(AT)));
   if (!st.p || RC < 1) return pass_y<NT, AT>(ncols, nin, Bd, T, alpha, z, beta, acc, scy, scx, out);
   double part = 0.0;
-  const int bw = al16(RC * w * (int)sizeof(AT));
+  const int bw = al16(RC * bstride * (int)sizeof(AT));
   L3<AT>* bs = (L3<AT>*)st.p;
   L3<TT>* rows = (L3<TT>*)(st.p + bw);
   const G<AT>* __restrict__ B = band_ptr<AT>(Bd);
@@ -365,9 +465,61 @@ __device__ double pass_y_st(int ncols, int nin, const BandDev& Bd, const TT* T, 
     int jlo, jhi;
     y_chunk(o0, rc, nin, lo, w, jlo, jhi);
     if (o0 > 0) __syncthreads();
-    stage_copy<NT>(bs, B + (int64_t)o0 * w, rc * w);
+    if (blk)
+      stage_band<NT, AT>(bs, B, o0, rc, w);
+    else
+      stage_copy<NT>(bs, B + (int64_t)o0 * w, rc * w);
     stage_copy<NT>(rows, T + (int64_t)jlo * ncols, (jhi - jlo + 1) * ncols);
     __syncthreads();
+    if (blk) {
+      // items (block of four output rows, column), the column fastest; two items per trip, whose
+      // other operands are all requested before the first output is formed
+      const int items = (rc + 3) / 4 * ncols;
+      for (int t0 = threadIdx.x; t0 < items; t0 += 2 * NT) {
+        AT zv[2][4], av[2][4];
+        double sc[2][4];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int t = t0 + q * NT, ob = t / ncols, c = t - ob * ncols;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int o = o0 + 4 * ob + i;
+            const bool ok = t < items && o < o0 + rc;
+            const int64_t ti = (int64_t)o * ncols + c;
+            zv[q][i] = (z && ok) ? (AT)z[ti] : (AT)0;
+            av[q][i] = (acc && ok) ? (AT)out[ti] : (AT)0;
+            sc[q][i] = (scy && ok) ? gp(scy)[o] * gp(scx)[c] : 1.0;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int t = t0 + q * NT;
+          const int ob = t / ncols, c = t - ob * ncols, oA = o0 + 4 * ob;
+          if (t < items) {
+            AT v[3 + kBandMax];
+            y_column<AT>(rows, ncols, nin, lo, jlo, jhi, oA, c, v);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int o = oA + i;
+              if (o < o0 + rc) {
+                const L3<AT>* bb = bs + (o - o0) * kBS;
+                AT s = 0;
+#pragma unroll
+                for (int d = 0; d < kBandMax; ++d) s += bb[d] * v[i + d];
+                AT vo = alpha * s;
+                if (scy) vo *= (AT)sc[q][i];
+                if (z) vo += beta * zv[q][i];
+                if (acc) vo += av[q][i];
+                out[(int64_t)o * ncols + c] = (OT)vo;
+                part += (double)vo * (double)vo;
+              }
+              __builtin_amdgcn_sched_barrier(0);  // one output's band row in registers at a time
+            }
+          }
+        }
+      }
+      continue;
+    }
     const int base = o0 * ncols, tot = rc * ncols;
     for (int t0 = own_from<NT>(base); t0 < tot; t0 += kStU * NT) {
       // the chunk's other operands, all requested before the first output is formed
@@ -412,9 +564,9 @@ template <int NT, typename AT, typename IT, typename OT>
 __device__ void pass_x2_st(int nrows, int nin, const BandDev& B1d, const BandDev& B2d, const IT* in, OT* out1,
                            OT* out2, Stg st) {
   const int nout = B1d.rows, w = B1d.w, lo = B1d.lo;
-  const int bw = al16(nout * w * (int)sizeof(AT));
+  const int bw = al16(nout * kBS * (int)sizeof(AT));
   const int RC = (st.bytes - 2 * bw) / (nin * (int)sizeof(IT));
-  if (!st.p || RC < 1) {
+  if (!st.p || RC < 1 || w > kBandMax) {
     pass_x2<NT, AT>(nrows, nin, B1d, B2d, in, out1, out2);
     return;
   }
@@ -422,24 +574,17 @@ __device__ void pass_x2_st(int nrows, int nin, const BandDev& B1d, const BandDev
   L3<AT>* b2 = (L3<AT>*)(st.p + bw);
   L3<IT>* rows = (L3<IT>*)(st.p + 2 * bw);
   __syncthreads();
-  stage_copy<NT>(b1, band_ptr<AT>(B1d), nout * w, b2, band_ptr<AT>(B2d));
+  stage_band<NT, AT>(b1, band_ptr<AT>(B1d), 0, nout, w, b2, band_ptr<AT>(B2d));
   for (int r0 = 0; r0 < nrows; r0 += RC) {
     const int rc = min(RC, nrows - r0);
     if (r0 > 0) __syncthreads();
     stage_copy<NT>(rows, in + (int64_t)r0 * nin, rc * nin);
     __syncthreads();
-    for (int t = threadIdx.x; t < rc * nout; t += NT) {
-      const int rr = t / nout, o = t - rr * nout;
-      AT s1 = 0, s2 = 0;
-      for (int d = 0; d < w; ++d) {
-        int j = o + lo + d;
-        j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
-        const AT v = (AT)rows[rr * nin + j];
-        s1 += b1[o * w + d] * v;
-        s2 += b2[o * w + d] * v;
-      }
-      out1[(int64_t)(r0 + rr) * nout + o] = (OT)s1;
-      out2[(int64_t)(r0 + rr) * nout + o] = (OT)s2;
+    const int nb = (rc + 3) / 4;
+    for (int t = threadIdx.x; t < nb * nout; t += NT) {
+      const int rb = t / nout, o = t - rb * nout;
+      x_block<AT, IT, OT, true>(b1, b2, rows, nin, lo, o, 4 * rb, min(4, rc - 4 * rb), out1, out2,
+                                (int64_t)r0 + 4 * rb, nout);
     }
   }
 }
@@ -450,10 +595,11 @@ __device__ double pass_y2_st(int ncols, int nin, const BandDev& B1d, const BandD
                              const TT* T2, AT a1, AT a2, const ZT* z, AT beta, OT* out, Stg st) {
   const int nout = B1d.rows, w = B1d.w, lo = B1d.lo;
   const int rowb = ncols * (int)sizeof(TT);
-  const int RC = min(nout, (st.bytes - 64 - 2 * (w - 1) * rowb) / (2 * rowb + 2 * w * (int)sizeof(AT)));
-  if (!st.p || RC < 1) return pass_y2<NT, AT>(ncols, nin, B1d, B2d, T1, T2, a1, a2, z, beta, out);
+  const int RC = min(nout, (st.bytes - 64 - 2 * (w - 1) * rowb) / (2 * rowb + 2 * kBS * (int)sizeof(AT)));
+  if (!st.p || RC < 1 || w > kBandMax)
+    return pass_y2<NT, AT>(ncols, nin, B1d, B2d, T1, T2, a1, a2, z, beta, out);
   double part = 0.0;
-  const int bw = al16(RC * w * (int)sizeof(AT));
+  const int bw = al16(RC * kBS * (int)sizeof(AT));
   L3<AT>* c1 = (L3<AT>*)st.p;
   L3<AT>* c2 = (L3<AT>*)(st.p + bw);
   const G<AT>* __restrict__ B1 = band_ptr<AT>(B1d);
@@ -467,34 +613,49 @@ __device__ double pass_y2_st(int ncols, int nin, const BandDev& B1d, const BandD
     L3<TT>* r1 = (L3<TT>*)(st.p + 2 * bw);
     L3<TT>* r2 = (L3<TT>*)(st.p + 2 * bw + al16(nr * rowb));
     if (o0 > 0) __syncthreads();
-    stage_copy<NT>(c1, B1 + (int64_t)o0 * w, rc * w, c2, B2 + (int64_t)o0 * w);
+    stage_band<NT, AT>(c1, B1, o0, rc, w, c2, B2);
     stage_copy<NT>(r1, T1 + (int64_t)jlo * ncols, nr * ncols, r2, T2 + (int64_t)jlo * ncols);
     __syncthreads();
-    const int base = o0 * ncols, tot = rc * ncols;
-    for (int t0 = own_from<NT>(base); t0 < tot; t0 += kStU * NT) {
-      AT zv[kStU];
+    const int items = (rc + 3) / 4 * ncols;
+    for (int t0 = threadIdx.x; t0 < items; t0 += 2 * NT) {
+      AT zv[2][4];
 #pragma unroll
-      for (int u = 0; u < kStU; ++u) {
-        const int t = t0 + u * NT;
-        zv[u] = (z && t < tot) ? (AT)z[(int64_t)base + t] : (AT)0;
+      for (int q = 0; q < 2; ++q) {
+        const int t = t0 + q * NT, ob = t / ncols, c = t - ob * ncols;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int o = o0 + 4 * ob + i;
+          zv[q][i] = (z && t < items && o < o0 + rc) ? (AT)z[(int64_t)o * ncols + c] : (AT)0;
+        }
       }
 #pragma unroll
-      for (int u = 0; u < kStU; ++u) {
-        const int t = t0 + u * NT;
-        if (t < tot) {
-          const int oo = t / ncols, c = t - oo * ncols, o = o0 + oo;
-          AT s1 = 0, s2 = 0;
-          for (int d = 0; d < w; ++d) {
-            int j = o + lo + d;
-            j = j < 0 ? 0 : (j >= nin ? nin - 1 : j);
-            s1 += c1[oo * w + d] * (AT)r1[(j - jlo) * ncols + c];
-            s2 += c2[oo * w + d] * (AT)r2[(j - jlo) * ncols + c];
+      for (int q = 0; q < 2; ++q) {
+        const int t = t0 + q * NT;
+        const int ob = t / ncols, c = t - ob * ncols, oA = o0 + 4 * ob;
+        if (t < items) {
+          AT v1[3 + kBandMax], v2[3 + kBandMax];
+          y_column<AT>(r1, ncols, nin, lo, jlo, jhi, oA, c, v1);
+          y_column<AT>(r2, ncols, nin, lo, jlo, jhi, oA, c, v2);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int o = oA + i;
+            if (o < o0 + rc) {
+              const L3<AT>* e1 = c1 + (o - o0) * kBS;
+              const L3<AT>* e2 = c2 + (o - o0) * kBS;
+              AT s1 = 0, s2 = 0;
+#pragma unroll
+              for (int d = 0; d < kBandMax; ++d) {
+                s1 += e1[d] * v1[i + d];
+                s2 += e2[d] * v2[i + d];
+              }
+              AT vo = a1 * s1;
+              if (z) vo += beta * zv[q][i];
+              vo += a2 * s2;
+              out[(int64_t)o * ncols + c] = (OT)vo;
+              part += (double)vo * (double)vo;
+            }
+            __builtin_amdgcn_sched_barrier(0);  // one output's band rows in registers at a time
           }
-          AT v = a1 * s1;
-          if (z) v += beta * zv[u];
-          v += a2 * s2;
-          out[(int64_t)base + t] = (OT)v;
-          part += (double)v * (double)v;
         }
       }
     }
