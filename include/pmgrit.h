@@ -104,7 +104,9 @@ typedef struct {
  * from the previous point, or the previous point itself if its FP64 residual is smaller (needs
  * pmgrit_net_load before solving).  With guess 3, sequential stepping predicts every step;
  * MGRIT predicts the level-0 F- and C-relaxation steps of its first iteration, step by step, and
- * uses guess 2 afterwards.
+ * uses guess 2 afterwards.  In MGRIT only instances of at most 64 elements per direction are
+ * predicted; the others take guess 2 throughout (there the previous point already needs as few
+ * V-cycles as the prediction, and the network's cost grows with the grid).
  * trsv_block: row-block size of the blocked triangular solves (0 = blocks of 64 consecutive
  * rows, the default; 1 = plain row level-scheduling; -1 = one grid line per block, split evenly
  * above 72 rows; k >= 2 = blocks of k rows). */

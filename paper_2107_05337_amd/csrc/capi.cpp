@@ -136,6 +136,7 @@ struct pmgrit_handle {
     // single-step lists of the learned warm start: level-0 F steps per position s in the
     // interval, and one step per instance (sequential stepping, shifted by k)
     std::vector<JobList> jF1;
+    JobList jC1;  // the level-0 C-steps of the learned first iteration (flags: which are predicted)
     JobList jSeq1;
     int max_jobs = 0;
     double* d_ws = nullptr;
@@ -929,6 +930,11 @@ static pmgrit_status learned_setup(pmgrit_handle* H) {
   TRY(upload<NetPick>(H, nullptr, kGivenMax, &H->d_pick_tmp));
   if (H->so.guess != 3) return PMGRIT_OK;
   const int m = H->m, N0 = H->Nl[0];
+  // MGRIT predicts only instances of at most kNetMaxElems elements per direction: at 128 and 256 the
+  // previous point already needs as few V-cycles per solve as the network's guess (2.0 against 2.0
+  // measured), and the inference's cost grows with the grid.  The others run their level-0 F-chains
+  // whole and take their targets (the previous iterate) as the guess
+  auto net_on = [&](int i) { return H->inst[i].prob.n_elems <= kNetMaxElems; };
   auto fsteps = [&](int i, int s, auto emit) {
     for (int j = 0; j * m + s + 1 <= N0 && s + 1 < m; ++j) emit(i, j * m + s);
   };
@@ -939,9 +945,22 @@ static pmgrit_status learned_setup(pmgrit_handle* H) {
     G.jF1.resize(std::max(m - 1, 1));
     for (int s = 0; s + 1 < m; ++s) {
       std::vector<PhiJob> J;
-      for (int i : G.inst) fsteps(i, s, [&](int ii, int k) { J.push_back({ii, 0, k, 1, 0, 0}); });
+      for (int i : G.inst) {
+        if (net_on(i)) {
+          fsteps(i, s, [&](int ii, int k) { J.push_back({ii, 0, k, 1, 0, 0}); });
+        } else if (s == 0) {
+          for (int j = 0; j * m < N0; ++j) {
+            const int len = std::min(m - 1, N0 - j * m);
+            if (len > 0) J.push_back({i, 0, j * m, len, 0, 1});
+          }
+        }
+      }
       TRY(upload_jobs(H, G, J, G.jF1[s]));
     }
+    std::vector<PhiJob> C1;
+    for (int i : G.inst)
+      for (int j = 1; j * m <= N0; ++j) C1.push_back({i, 0, j * m - 1, 1, 0, net_on(i) ? 0 : 1});
+    TRY(upload_jobs(H, G, C1, G.jC1));
     std::vector<PhiJob> S1;
     for (int i : G.inst) S1.push_back({i, 0, 0, 1, 0, 0});
     TRY(upload_jobs(H, G, S1, G.jSeq1));
@@ -962,7 +981,7 @@ static pmgrit_status learned_setup(pmgrit_handle* H) {
     std::vector<NetPick> seq, c;
     for (int i : N.inst) {
       seq.push_back({i, 0});
-      csteps(i, [&](int ii, int k) { c.push_back({ii, k}); });
+      if (net_on(i)) csteps(i, [&](int ii, int k) { c.push_back({ii, k}); });
     }
     TRY(upload_vec(H, seq, &N.d_seq));
     TRY(upload_vec(H, c, &N.d_c));
@@ -971,7 +990,8 @@ static pmgrit_status learned_setup(pmgrit_handle* H) {
     N.nf.assign(std::max(m - 1, 1), 0);
     for (int s = 0; s + 1 < m; ++s) {
       std::vector<NetPick> f;
-      for (int i : N.inst) fsteps(i, s, [&](int ii, int k) { f.push_back({ii, k}); });
+      for (int i : N.inst)
+        if (net_on(i)) fsteps(i, s, [&](int ii, int k) { f.push_back({ii, k}); });
       TRY(upload_vec(H, f, &N.d_f[s]));
       N.nf[s] = (int)f.size();
     }
@@ -1801,7 +1821,7 @@ static hipError_t relax_level0(pmgrit_handle* h, hipStream_t st, bool learned, i
     };
     if ((e = fsplit()) != hipSuccess) return e;
     if ((e = net_predict(h, 2, 0, 0, st)) != hipSuccess) return e;
-    if ((e = sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jC[0]; }, kModeChain, st, 4)) !=
+    if ((e = sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jC1; }, kModeChain, st, 4)) !=
         hipSuccess)
       return e;
     if ((e = fsplit()) != hipSuccess) return e;

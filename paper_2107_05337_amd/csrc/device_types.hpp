@@ -22,6 +22,8 @@ constexpr int kWinBlock = 128;
 constexpr int kSbufWords = 320;
 // LDS staging area of the exact p = 1 solve's dense transforms (doubles)
 constexpr int kStageDoubles = 2048;
+// largest mesh (elements per direction) whose level-0 steps MGRIT's learned warm start predicts
+constexpr int kNetMaxElems = 64;
 constexpr int kBandStageMin = 16 * 1024;  // smallest LDS staging area of the band passes (bytes)
 // slab tables of the window-mode triangular solves: 8 KB chunks (one 16-byte load per lane of a
 // 512-thread workgroup), at most kDch per level, the first slab at value kSlab0 of dfast
@@ -137,7 +139,8 @@ struct InstDev {
 // starting from point k0 (reads V[k0], writes V[k0+1], ... V[k0+len]); in residual mode one
 // step whose result minus V[k0+1] goes to point outj of the next level's right-hand side.
 struct PhiJob {
-  int inst, level, k0, len, outj, pad;
+  int inst, level, k0, len, outj;
+  int flags;  // bit 0: the job's targets hold no network prediction (guess mode 4 acts as mode 2)
 };
 // guess modes of PhiParams::guess: 0 zero, 1 previous point, 2 current target (level 0) /
 // previous point (coarse levels), 4 the better of the current target and the previous point by

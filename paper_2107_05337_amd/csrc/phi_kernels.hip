@@ -1858,7 +1858,7 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
       // leaves the smaller residual
       const bool prev = P.guess == 1 || (P.guess >= 2 && job.level > 0);
       for (int i = threadIdx.x; i < n; i += NT) x[i] = prev ? vk[i] : (P.guess >= 2 ? tgt[i] : 0.0);
-      if (P.guess == 4 && job.level == 0) {
+      if (P.guess == 4 && job.level == 0 && !(job.flags & 1)) {
         __syncthreads();
         double* rt = sizeof(VT) == 8 ? (double*)r : (double*)(ws + 5 * nm);  // FP64 residual temp
         const double ra = block_sum<NT>(apply_A<NT, double, OCC>(I, L, x, b, rt, yd), red);
