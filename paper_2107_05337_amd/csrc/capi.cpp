@@ -151,6 +151,7 @@ struct pmgrit_handle {
     hipEvent_t done = nullptr;
   };
   std::vector<Group> groups;
+  std::vector<int> launch_order;  // groups by decreasing cost: each sweep launches the costliest first
   std::vector<int> inst_group;
   // learned warm start: the network and, per grid size, the samples of the single-step lists
   std::unique_ptr<NetState> net;
@@ -1071,6 +1072,15 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
       H->groups.push_back(std::move(G));
     }
   }
+  {
+    // the launch groups' cost, n_dof (2p + 1) summed over their instances (the job order's measure)
+    std::vector<double> cost(H->groups.size(), 0.0);
+    for (size_t g = 0; g < H->groups.size(); ++g)
+      for (int i : H->groups[g].inst) cost[g] += (double)H->inst[i].ndof * (2 * H->inst[i].p + 1);
+    H->launch_order.resize(H->groups.size());
+    for (size_t g = 0; g < H->groups.size(); ++g) H->launch_order[g] = (int)g;
+    std::stable_sort(H->launch_order.begin(), H->launch_order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  }
   H->h_instdev.resize(H->ninst);
   for (int i = 0; i < H->ninst; ++i) {
     InstHost& I = H->inst[i];
@@ -1354,7 +1364,8 @@ static hipError_t sweep(pmgrit_handle* H, Pick pick, int mode, hipStream_t st, i
   if (active == 0) return hipSuccess;
   const bool fork = active > 1;
   if (fork && (e = hipEventRecord(H->fork, st)) != hipSuccess) return e;
-  for (pmgrit_handle::Group& G : H->groups) {
+  for (int gi : H->launch_order) {
+    pmgrit_handle::Group& G = H->groups[gi];
     const pmgrit_handle::JobList& J = pick(G);
     if (J.n == 0) continue;
     hipStream_t gs = fork ? G.stream : st;
