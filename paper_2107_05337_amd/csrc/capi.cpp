@@ -413,7 +413,7 @@ static pmgrit_status setup_level(const pmgrit_handle* H, InstHost& I, int l, std
     // each level waits on table loads from HBM: blocks of 128 rows halve the dependent levels.
     // (FP32 V-cycles only: the FP64 window solve keeps 64-row blocks, see kWinDense)
     const bool window = (int64_t)I.ndof * 8 + 16 + 512 + kSbufWords * 8 > (int64_t)kLdsBytes;
-    bs = std::min(I.ndof, window && H->so.precision == 1 ? kWinBlock : kWaveBlock);
+    bs = std::min(I.ndof, window ? kWinBlock : kWaveBlock);
   } else if (bs == -1) {
     // one grid line per block, split evenly when a line exceeds the prefetched path's 72 rows
     const int parts = (I.Nin + kDenseMax - 1) / kDenseMax;
@@ -631,7 +631,7 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
   for (int c : S.dq0) maxq = std::max(maxq, c);
   const size_t aslots = ((size_t)S.nlev * std::max(1, S.max_rows) + 1) * (size_t)RW;
   T.fast = (zidx >= 0 && S.max_rows <= kRowSlots && maxo <= RW && maxo <= kOffMax &&
-            maxd <= ((winW > 0 && H->fp32) ? kDenseWin : kDenseMax) &&
+            maxd <= (winW > 0 ? kDenseWin : kDenseMax) &&
             maxq < 65536 && S.dval.size() + 1 < (size_t)INT32_MAX && aslots * sizeof(double) < (size_t)kBufBytes &&
             (winW == 0 || window_fits(S, winW, winN)))
                ? 1
@@ -695,24 +695,25 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
           acol[(1 + sl) * AS + t] = colmap(S.oci[S.orp[q] + t]) - zidx;
         }
       }
-    // FP32 window mode, 512 threads of 4 lanes per row: slab tables when a level's dense rows fit
-    // kDch chunks and the window columns 16 bits
+    // window mode, 512 threads of 4 lanes per row: slab tables when a level's dense rows fit kDch
+    // chunks (twice as many in FP64) and the window columns 16 bits
     T.dch = 0;
     T.lsv = 0;
     T.acol16 = nullptr;
-    if (T.winW > 0 && H->fp32 && TGh == 4 && R * TGh == 512 && AS % TGh == 0) {
+    const int vb = H->fp32 ? 4 : 8, dchmax = H->fp32 ? kDch : 2 * kDch;
+    if (T.winW > 0 && TGh == 4 && R * TGh == 512 && AS % TGh == 0) {
       size_t maxlev = 0;
       for (int l = 0; l < S.nlev; ++l) {
         size_t sum = 0;
         for (int q = S.lev_ptr[l]; q < S.lev_ptr[l + 1]; ++q) sum += (size_t)TGh * (meta[1 + (size_t)l * R + (q - S.lev_ptr[l])].bqc >> 16);
         maxlev = std::max(maxlev, sum);
       }
-      const int dch = (int)((maxlev * 4 + kChunkBytes - 1) / kChunkBytes);
+      const int dch = (int)((maxlev * vb + kChunkBytes - 1) / kChunkBytes);
       bool c16 = true;
       for (int c : acol) c16 = c16 && c >= -32768 && c <= 32767;
-      const int lsv = std::max(1, dch) * (kChunkBytes / 4);
+      const int lsv = std::max(1, dch) * (kChunkBytes / vb);
       const size_t slab_vals = (size_t)kSlab0 + (size_t)S.nlev * lsv;
-      if (dch >= 1 && dch <= kDch && c16 && slab_vals * sizeof(double) < (size_t)kBufBytes) {
+      if (dch >= 1 && dch <= dchmax && c16 && slab_vals * sizeof(double) < (size_t)kBufBytes) {
         std::vector<double> slab(slab_vals, 0.0);
         for (int l = 0; l < S.nlev; ++l) {
           size_t at = (size_t)kSlab0 + (size_t)l * lsv;
@@ -740,6 +741,8 @@ static pmgrit_status upload_tri(pmgrit_handle* H, const TriSchedule& S, TriDev& 
         T.lsv = lsv;
       }
     }
+    // FP64 dense rows wider than the register path takes run only on slab tables
+    if (!H->fp32 && maxd > kDenseMax && T.dch == 0) T.fast = 0;
     T.R = R;
     T.AS = AS;
     Meta4* m4;

@@ -28,7 +28,9 @@ constexpr int kBandStageMin = 16 * 1024;  // smallest LDS staging area of the ba
 // slab tables of the window-mode triangular solves: 8 KB chunks (one 16-byte load per lane of a
 // 512-thread workgroup), at most kDch per level, the first slab at value kSlab0 of dfast
 constexpr int kChunkBytes = 8192;
-constexpr int kDch = 5;
+constexpr int kDch = 5;  // FP32
+template <typename VT>
+constexpr int kDchOf = sizeof(VT) == 4 ? kDch : 2 * kDch;
 constexpr int kSlab0 = kChunkBytes / 4;
 // LDS per workgroup of gfx950 (160 KiB)
 constexpr int kLdsBytes = 160 * 1024;

@@ -1021,14 +1021,17 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
 // bytes), so these take about a third fewer instructions.  The off-block rows are requested one level
 // ahead, the right-hand sides and slabs two levels ahead (two register sets, even and odd levels),
 // the metadata three.  The arithmetic is trsv_fast's, in the same order.
-template <int KA>
-__device__ __noinline__ void trsv_slab(const TriDev* __restrict__ Tp, int zidx, const float* in_g, L3<float>* y,
-                                       L3<float>* sbuf, float* yg, L3<float>* dst) {
-  typedef float VT;
-  constexpr int TG = 4, RW = KA * TG, V = 4, WA = KA < V ? KA : V, NU = KA / WA, CB = KA * 2;
+template <typename VT, int KA>
+__device__ __noinline__ void trsv_slab(const TriDev* __restrict__ Tp, int zidx, const VT* in_g, L3<VT>* y,
+                                       L3<VT>* sbuf, VT* yg, L3<VT>* dst) {
+  constexpr int VB = (int)sizeof(VT), TG = 4, RW = KA * TG, V = 16 / VB, WA = KA < V ? KA : V, NU = KA / WA;
+  constexpr int CB = KA * 2, DCH = kDchOf<VT>;
+  // register sets of slabs in flight: two (two levels ahead) in FP32; one (one level ahead) in FP64,
+  // whose slabs are twice as large
+  constexpr int SETS = VB == 4 ? 2 : 1;
   constexpr int BCM = (kDenseWin + V - 1 + TG * V - 1) / (TG * V) * V, ND = BCM / V;
   static_assert(kRowSlots - 1 + TG * BCM <= kSbufWords, "sbuf too small for the dense rows");
-  typedef VT VV __attribute__((ext_vector_type(4)));
+  typedef VT VV __attribute__((ext_vector_type(V)));
   typedef unsigned U4 __attribute__((ext_vector_type(4)));
   Tp = uniform_ptr(Tp);
   const __amdgpu_buffer_rsrc_t rval = table_rsrc(Tp->aval), rc16 = table_rsrc(Tp->acol16),
@@ -1054,10 +1057,15 @@ __device__ __noinline__ void trsv_slab(const TriDev* __restrict__ Tp, int zidx, 
 #pragma unroll
     for (int k = 0; k < NU; ++k) {
       const int e0 = (k * TG + g) * WA;
-      unsigned uv[WA];
-      buf_load<WA * 4>(rval, e0 < m.na ? (base + e0) * 4 : kOff, uv);
+      unsigned uv[WA * VB / 4];
+      buf_load<WA * VB>(rval, e0 < m.na ? (base + e0) * VB : kOff, uv);
 #pragma unroll
-      for (int e = 0; e < WA; ++e) av[k * WA + e] = __builtin_bit_cast(float, uv[e]);
+      for (int e = 0; e < WA; ++e) {
+        if constexpr (VB == 8)
+          av[k * WA + e] = __builtin_bit_cast(double, ((unsigned long long)uv[2 * e + 1] << 32) | uv[2 * e]);
+        else
+          av[k * WA + e] = __builtin_bit_cast(float, uv[e]);
+      }
     }
     // lane g's columns (k * WA + e order) at (base + g * KA) * 2 bytes, zero past the row's entries
     const bool live = l < nlev;
@@ -1071,15 +1079,18 @@ __device__ __noinline__ void trsv_slab(const TriDev* __restrict__ Tp, int zidx, 
   };
   // the row's right-hand side, by the lane that writes its result (it holds the raw record)
   auto load_x = [&](const Meta4& m, VT& xin) {
-    unsigned u[1];
-    buf_load<4>(rin, g == 0 && m.row >= 0 ? m.row * 4 : kOff, u);
-    xin = __builtin_bit_cast(float, u[0]);
+    unsigned u[VB / 4];
+    buf_load<VB>(rin, g == 0 && m.row >= 0 ? m.row * VB : kOff, u);
+    if constexpr (VB == 8)
+      xin = __builtin_bit_cast(double, ((unsigned long long)u[1] << 32) | u[0]);
+    else
+      xin = __builtin_bit_cast(float, u[0]);
   };
   auto load_d = [&](int l, U4* dr) {
-    const int b0 = (kSlab0 + l * lsv) * 4 + (int)threadIdx.x * 16;
+    const int b0 = (kSlab0 + l * lsv) * VB + (int)threadIdx.x * 16;
     const bool live = l < nlev;
 #pragma unroll
-    for (int c = 0; c < kDch; ++c) {
+    for (int c = 0; c < DCH; ++c) {
       unsigned u[4];
       buf_load<16>(rden, live && c < dch ? b0 + c * kChunkBytes : kOff, u);
       dr[c] = U4{u[0], u[1], u[2], u[3]};
@@ -1087,7 +1098,7 @@ __device__ __noinline__ void trsv_slab(const TriDev* __restrict__ Tp, int zidx, 
   };
   auto store_d = [&](const U4* dr) {
 #pragma unroll
-    for (int c = 0; c < kDch; ++c) ((L3<U4>*)dst)[c * (kChunkBytes / 16) + threadIdx.x] = dr[c];
+    for (int c = 0; c < DCH; ++c) ((L3<U4>*)dst)[c * (kChunkBytes / 16) + threadIdx.x] = dr[c];
   };
   auto phase_a = [&](const VT* av, const int* ac, int row, VT xin) {
     VT s = 0;
@@ -1122,7 +1133,7 @@ __device__ __noinline__ void trsv_slab(const TriDev* __restrict__ Tp, int zidx, 
   // other set)
   VT av[KA], x0, x1;
   int ac[KA];
-  U4 d0[kDch], d1[kDch];
+  U4 d0[DCH], d1[SETS == 2 ? DCH : 1];
   Meta4 C, N, N2;
   load_meta(0, C);
   load_meta(1, N);
@@ -1134,7 +1145,7 @@ __device__ __noinline__ void trsv_slab(const TriDev* __restrict__ Tp, int zidx, 
   load_a(0, C, av, ac);
   __builtin_amdgcn_sched_barrier(0);
   load_d(0, d0);
-  load_d(1, d1);
+  if constexpr (SETS == 2) load_d(1, d1);
   __builtin_amdgcn_sched_barrier(0);
   // one level: phase A, its slab into LDS, level l + 1's off-block rows requested, phase B from LDS,
   // then level l + 3's metadata and level l + 2's right-hand side and slab
@@ -1150,7 +1161,7 @@ __device__ __noinline__ void trsv_slab(const TriDev* __restrict__ Tp, int zidx, 
     Meta4 N3;
     load_meta(l + 3, N3);
     load_x(N2, xin);
-    load_d(l + 2, dr);
+    load_d(l + SETS, dr);
     C = N;
     N = N2;
     N2 = N3;
@@ -1159,7 +1170,7 @@ __device__ __noinline__ void trsv_slab(const TriDev* __restrict__ Tp, int zidx, 
   for (int l = 0; l < nlev; l += 2) {
     level(l, x0, d0);
     if (l + 1 >= nlev) break;
-    level(l + 1, x1, d1);
+    level(l + 1, x1, SETS == 2 ? d1 : d0);
   }
 }
 
@@ -1220,26 +1231,28 @@ __device__ __forceinline__ void trsv(const TriDev& T, int ka, int zidx, const VT
   } else if (!YLDS && IN_GLOBAL && (OCC == 1 || OCC == 2) && win && T.fast && T.winW > 0) {
     L3<VT>* wl = (L3<VT>*)win;
     bool slab = false;
-    if constexpr (sizeof(VT) == 4 && OCC == 1) {
+    if constexpr (OCC == 1) {
       // slab tables, with the band-pass staging area as the slabs' LDS area
-      if (T.dch > 0 && T.R * 4 == Build<OCC>::NT && st.p && st.bytes >= kDch * kChunkBytes) {
+      if (T.dch > 0 && T.R * 4 == Build<OCC>::NT && st.p && st.bytes >= kDchOf<VT> * kChunkBytes) {
         slab = true;
-        const float* inf = (const float*)in;
-        L3<float>* wf = (L3<float>*)win;
-        L3<float>* sf = (L3<float>*)sbuf;
-        float* yf = (float*)y;
-        L3<float>* ds = (L3<float>*)st.p;
+        L3<VT>* sf = (L3<VT>*)sbuf;
+        L3<VT>* ds = (L3<VT>*)st.p;
         if (ka <= 2)
-          trsv_slab<2>(&T, zwin, inf, wf, sf, yf, ds);
+          trsv_slab<VT, 2>(&T, zwin, in, wl, sf, y, ds);
         else if (ka <= 4)
-          trsv_slab<4>(&T, zwin, inf, wf, sf, yf, ds);
+          trsv_slab<VT, 4>(&T, zwin, in, wl, sf, y, ds);
         else if (ka <= 8)
-          trsv_slab<8>(&T, zwin, inf, wf, sf, yf, ds);
+          trsv_slab<VT, 8>(&T, zwin, in, wl, sf, y, ds);
         else if (ka <= 12)
-          trsv_slab<12>(&T, zwin, inf, wf, sf, yf, ds);
+          trsv_slab<VT, 12>(&T, zwin, in, wl, sf, y, ds);
         else
-          trsv_slab<16>(&T, zwin, inf, wf, sf, yf, ds);
+          trsv_slab<VT, 16>(&T, zwin, in, wl, sf, y, ds);
       }
+    }
+    if (!slab && sizeof(VT) == 8 && T.dch > 0) {
+      // FP64 slab tables hold dense rows wider than the register path takes: the general path
+      slab = true;
+      trsv_general<VT, Build<OCC>::NT>(T, in, y, sbuf);
     }
     if (!slab) {
       if (ka <= 2)

@@ -328,6 +328,28 @@ def test_w8_build_needs_64_row_levels(torch):
     S.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_window_mode_slab_tables(torch, precision):
+    """An instance too large for LDS (p = 3, n = 150: window mode by default, 128-row blocks) in FP64 and
+    FP32-refined: the triangular solves run over slab tables (each level's dense rows copied to LDS in
+    8 KB chunks, 16-bit window columns) and the trajectory reaches the oracle's."""
+    cfg = W.small("x", 3, 150, 16)
+    d = cfg["instances"][0]
+    say(f"case window mode, slab tables, p=3 n=150 N_t=16 precision {precision}")
+    P = O.Problem(d["p"], d["n"], d["domain"])
+    Us = P.sequential(d["kappa"], d["T"], d["Nt"], P.load_vector(d["src"]), d["tkind"], P.project(d["init"]))
+    S = make_solver(cfg, precision=precision, tol=1e-12, stol=1e-13)
+    sch = S.host_schedule()
+    gi = S.group_info(0)
+    (U,), st = S.solve_mgrit()
+    e = rel(U.cpu().numpy(), Us)
+    say(f"  block {sch['block_size']} levels {sch['levels']} mask {gi['lds_mask']}: iters {st['mgrit_iters']} "
+        f"V-cycles {st['vcycles']} eps {e:.2e}")
+    assert gi["lds_mask"] & 1 == 0 and sch["block_size"] == 128
+    assert e <= 1e-10
+    S.close()
+
+
 def test_window_mode_128_row_blocks(torch):
     """FP32 triangular solves in window mode (y in global memory, mask 2) with 128-row blocks (the block
     size instances too large for LDS get): the trajectory reaches the oracle's, as with the default

@@ -244,10 +244,10 @@ def test_theta_level_operator_matches_oracle(theta):
         assert abs(A - Ao).max() <= 1e-13 * abs(Ao).max()
 
 
-@pytest.mark.parametrize("precision,bs", [(1, 128), (0, 64)])
+@pytest.mark.parametrize("precision,bs", [(1, 128), (0, 128)])
 def test_window_instances_get_128_row_blocks(precision, bs):
     """An instance whose FP64-sized triangular-solve vector cannot be in LDS (h = 2^-8) is scheduled in
-    blocks of 128 rows for the FP32 V-cycle (window mode), 64 otherwise"""
+    blocks of 128 rows in either precision (window mode, slab tables), 64 otherwise"""
     S = host_solver(2, 256, Nt=8, trsv_block=0, precision=precision)
     s = S.host_schedule()
     assert s["block_size"] == bs and s["max_rows"] <= 128
