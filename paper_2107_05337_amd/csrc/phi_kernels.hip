@@ -1013,14 +1013,15 @@ __device__ __noinline__ void trsv_fast(const TriDev* __restrict__ Tp, int zidx, 
 }
 
 
-// FP32 window-mode solve over slab tables (TriDev::dch > 0; 512 threads, 4 lanes per row, 128 row slots).
+// Window-mode solve over slab tables (TriDev::dch > 0; 512 threads, 4 lanes per row, 128 row slots).
 // A level's dense rows lie contiguous in a slab of dch x 8 KB, which the whole workgroup copies into
 // the LDS area dst with one 16-byte load per lane per 8 KB, so the dense rows cost no loads for their
 // padding lanes; the off-block columns are 16 bits, each lane's KA of them contiguous.  A level of
 // the window mode is bound by the CU's vector-memory path (instructions, padding lanes included, and
 // bytes), so these take about a third fewer instructions.  The off-block rows are requested one level
-// ahead, the right-hand sides and slabs two levels ahead (two register sets, even and odd levels),
-// the metadata three.  The arithmetic is trsv_fast's, in the same order.
+// ahead, the right-hand sides two levels ahead, the metadata three, and the slabs two levels ahead in
+// FP32 (two register sets, even and odd levels) and one in FP64 (slabs twice as large).  The
+// arithmetic is trsv_fast's, in the same order.
 template <typename VT, int KA>
 __device__ __noinline__ void trsv_slab(const TriDev* __restrict__ Tp, int zidx, const VT* in_g, L3<VT>* y,
                                        L3<VT>* sbuf, VT* yg, L3<VT>* dst) {
