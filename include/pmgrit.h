@@ -189,7 +189,10 @@ pmgrit_status pmgrit_set_initial_coeffs(pmgrit_handle* h, int32_t inst, const do
 
 /* MGRIT solve of every instance (Sec. 3).  u_out_dev[i] is instance i's trajectory buffer of
  * (N_t + 1) x n_dof doubles on the device; on return (after the stream is synchronised by the
- * call) it holds the converged trajectory.  stats may be NULL. */
+ * call) it holds the converged trajectory.  Each instance stops on its own criterion: once its
+ * relative C-point residual reaches tol, its trajectory is kept as it is while the others
+ * iterate, so a batched instance returns what a solve of it alone would (mgrit_iters and
+ * res_hist describe the slowest instance).  stats may be NULL. */
 pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* const* u_out_dev, pmgrit_stats* stats);
 
 /* Sequential implicit Euler with the same spatial solver (block forward solve of eq:mgrit);

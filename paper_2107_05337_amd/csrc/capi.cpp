@@ -25,7 +25,8 @@ hipError_t phi_launch(int fp32, int mask, int lds_bytes, const PhiParams& P, con
                       hipStream_t st);
 hipError_t fill_launch(double* p, int64_t n, double v, hipStream_t st);
 hipError_t copy_launch(double* dst, const double* src, int64_t n, hipStream_t st);
-hipError_t correct_launch(double* Vl, const double* Vc, int ndof, int m, int ncoarse, hipStream_t st);
+hipError_t correct_launch(double* Vl, const double* Vc, int ndof, int m, int ncoarse, const int* frozen,
+                          hipStream_t st);
 hipError_t norm_reduce_launch(const double* nrm2, const int* begin, const int* id, double* out, int ninst,
                               hipStream_t st);
 hipError_t scratch_setup(int device);
@@ -107,6 +108,10 @@ struct pmgrit_handle {
   std::vector<double*> h_vtab, h_gtab;
   int* d_status = nullptr;
   double* d_resnorm = nullptr;
+  // MGRIT: per instance, converged (its jobs and corrections skip it) while freeze_on is set
+  int* d_frozen = nullptr;
+  int* h_frozen = nullptr;  // pinned host copy of the flags
+  bool freeze_on = false;
   double* h_pinned = nullptr;  // residual norms read back per MGRIT iteration
   PhiJob* h_given_jobs = nullptr;
   int given_key[3] = {-1, -1, -1};
@@ -1273,8 +1278,10 @@ static pmgrit_status device_setup(pmgrit_handle* H) {
   HIPCHK(hipEventCreateWithFlags(&H->gjoin, hipEventDisableTiming));
   TRY(upload<int>(H, nullptr, 4, &H->d_status));
   TRY(upload<double>(H, nullptr, (size_t)H->ninst, &H->d_resnorm));
+  TRY(upload<int>(H, nullptr, (size_t)H->ninst, &H->d_frozen));
   HIPCHK(hipMemset(H->d_status, 0, sizeof(int) * 4));
   HIPCHK(hipHostMalloc((void**)&H->h_pinned, sizeof(double) * (H->ninst + 8), 0));
+  HIPCHK(hipHostMalloc((void**)&H->h_frozen, sizeof(int) * (H->ninst + 8), 0));
   HIPCHK(hipHostMalloc((void**)&H->h_given_jobs, sizeof(PhiJob) * kGivenMax, 0));
   H->ev.resize(2048);
   for (auto& e : H->ev) HIPCHK(hipEventCreate(&e));
@@ -1374,6 +1381,7 @@ static hipError_t sweep(pmgrit_handle* H, Pick pick, int mode, hipStream_t st, i
     hipStream_t gs = fork ? G.stream : st;
     if (fork && (e = hipStreamWaitEvent(gs, H->fork, 0)) != hipSuccess) return e;
     PhiParams P = base_params(H, G, mode, J.d);
+    if (H->freeze_on) P.frozen = H->d_frozen;
     if (guess >= 0) P.guess = guess;
     P.kshift = kshift;
     if ((e = phi_timed(H, G, P, J.n, gs)) != hipSuccess) return e;
@@ -1434,7 +1442,9 @@ static hipError_t mgrit_cycle(pmgrit_handle* H, int l, int kind, hipStream_t st,
   for (int i = 0; i < H->ninst; ++i) {
     double* vl = H->h_vtab[(size_t)i * kMaxLevels + l];
     double* vc = H->h_vtab[(size_t)i * kMaxLevels + l + 1];
-    if ((e = correct_launch(vl, vc, H->inst[i].ndof, H->m, H->Nl[l + 1], st)) != hipSuccess) return e;
+    if ((e = correct_launch(vl, vc, H->inst[i].ndof, H->m, H->Nl[l + 1], H->freeze_on ? H->d_frozen + i : nullptr,
+                            st)) != hipSuccess)
+      return e;
   }
   // ideal interpolation = F-relaxation from the corrected C-points
   phi += sweep_steps(H, 0, l);
@@ -1701,6 +1711,7 @@ void pmgrit_destroy(pmgrit_handle* h) {
     (void)hipDeviceSynchronize();
     for (void* p : h->allocs) (void)hipFree(p);
     if (h->h_pinned) (void)hipHostFree(h->h_pinned);
+    if (h->h_frozen) (void)hipHostFree(h->h_frozen);
     if (h->h_given_jobs) (void)hipHostFree(h->h_given_jobs);
     if (h->h_netsrc) (void)hipHostFree(h->h_netsrc);
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
@@ -1869,7 +1880,9 @@ static hipError_t correct_level0(pmgrit_handle* h, hipStream_t st, double* const
   if ((e = level_solve(h, 1, h->mo.cycle, st, phi)) != hipSuccess) return e;
   for (int i = 0; i < h->ninst; ++i) {
     double* vc = h->h_vtab[(size_t)i * kMaxLevels + 1];
-    if ((e = correct_launch(u_out[i], vc, h->inst[i].ndof, h->m, h->Nl[1], st)) != hipSuccess) return e;
+    if ((e = correct_launch(u_out[i], vc, h->inst[i].ndof, h->m, h->Nl[1], h->freeze_on ? h->d_frozen + i : nullptr,
+                            st)) != hipSuccess)
+      return e;
   }
   return hipSuccess;
 }
@@ -1951,6 +1964,14 @@ pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* con
     phi += sweep_steps(h, 4, 0);
   } else {
     const bool graph = h->mo.use_graph != 0;
+    // an instance whose residual reaches the tolerance keeps that iterate: from the next
+    // iteration on, its jobs and corrections are skipped (the flags are read at replay, so the
+    // captured graph holds the flag array too)
+    h->freeze_on = true;
+    struct Unfreeze {
+      pmgrit_handle* h;
+      ~Unfreeze() { h->freeze_on = false; }
+    } unfreeze{h};  // every exit, the error returns included, leaves the other entry points unaffected
     if (graph) {
       // the whole solve runs on the library's own stream, ordered after the caller's work
       HIPCHK(hipEventRecord(h->gfork, st));
@@ -1960,21 +1981,34 @@ pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* con
       forked = true;
       TRY(capture_iteration(h, st, u_out_dev));
     }
-    std::vector<double> r0(h->ninst, -1.0);
+    std::vector<double> r0(h->ninst, -1.0), rfix(h->ninst, 0.0);
+    std::memset(h->h_frozen, 0, sizeof(int) * h->ninst);
+    HIPCHK(hipMemcpyAsync(h->d_frozen, h->h_frozen, sizeof(int) * h->ninst, hipMemcpyHostToDevice, st));
     HIPCHK(relax_level0(h, st, h->so.guess == 3, phi));
     for (;;) {
       HIPCHK(hipMemcpyAsync(h->h_pinned, h->d_resnorm, sizeof(double) * h->ninst, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       HIPCHK(harvest(h));
-      bool done = true, bad = false;
+      bool done = true, bad = false, newly = false;
       double worst = 0.0;
       for (int i = 0; i < h->ninst; ++i) {
+        if (h->h_frozen[i]) {
+          // no residual was computed for it: its value at freezing stands
+          worst = std::max(worst, rfix[i]);
+          continue;
+        }
         double rn = std::sqrt(h->h_pinned[i]);
         if (!std::isfinite(rn)) bad = true;
         if (r0[i] < 0) r0[i] = rn;
         double rel = r0[i] > 0 ? rn / r0[i] : 0.0;
         worst = std::max(worst, rel);
-        if (!(rn <= h->mo.tol * r0[i] || r0[i] == 0.0)) done = false;
+        if (rn <= h->mo.tol * r0[i] || r0[i] == 0.0) {
+          h->h_frozen[i] = 1;
+          rfix[i] = rel;
+          newly = true;
+        } else {
+          done = false;
+        }
       }
       if (iters < 64) S.res_hist[iters] = worst;
       pmgrit_status s = read_status(h, st);
@@ -1991,13 +2025,21 @@ pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* con
         rc = fail(PMGRIT_E_MGRIT_NOCONV, "MGRIT reached max_iter");
         break;
       }
+      if (newly)
+        HIPCHK(hipMemcpyAsync(h->d_frozen, h->h_frozen, sizeof(int) * h->ninst, hipMemcpyHostToDevice, st));
+      // every instance has the same N_t, so it takes the same share of every sweep's solves;
+      // frozen instances take none
+      int64_t it_phi = 0;
       if (graph) {
         HIPCHK(graph_launch_timed(h, st));
-        phi += h->graph_phi;
+        it_phi = h->graph_phi;
       } else {
-        HIPCHK(correct_level0(h, st, u_out_dev, phi));
-        HIPCHK(relax_level0(h, st, false, phi));
+        HIPCHK(correct_level0(h, st, u_out_dev, it_phi));
+        HIPCHK(relax_level0(h, st, false, it_phi));
       }
+      int active = 0;
+      for (int i = 0; i < h->ninst; ++i) active += h->h_frozen[i] ? 0 : 1;
+      phi += it_phi / h->ninst * active;
       ++iters;
     }
   }

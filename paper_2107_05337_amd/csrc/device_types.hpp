@@ -161,6 +161,7 @@ struct PhiParams {
   int* vcount;             // V-cycles per workgroup (accumulated)
   int* vlast;              // mode kModeGiven: V-cycles of this solve per workgroup (may be null)
   unsigned long long* vinst;  // V-cycles per instance (accumulated since create)
+  const int* frozen;          // MGRIT: instances already converged (their jobs return at once; null: none)
   int* status;             // error flags (bit 0 non-finite, bit 1 V-cycle cap)
   double* ws;              // per-workgroup global scratch
   int64_t ws_stride;       // doubles per workgroup

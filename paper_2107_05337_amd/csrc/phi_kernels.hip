@@ -1792,6 +1792,8 @@ __device__ __forceinline__ void phi_body(const PhiParams& P, const LdsPlan& plan
   constexpr int NT = Build<OCC>::NT;
   extern __shared__ __align__(16) unsigned char smem[];
   const PhiJob job = P.jobs[blockIdx.x];
+  // an instance whose MGRIT residual has reached the tolerance is left as it is
+  if (P.frozen && P.frozen[job.inst]) return;
   const InstDev& I = P.inst[job.inst];
   const LevelDev& L = I.lev[job.level];
   const int n = I.ndof;
@@ -1993,7 +1995,8 @@ __global__ void copy_kernel(double* __restrict__ dst, const double* __restrict__
 
 // coarse-grid correction of the C-points: V_l[j m] += V_{l+1}[j], j = 1 .. ncoarse
 __global__ void correct_kernel(double* __restrict__ Vl, const double* __restrict__ Vc, int ndof, int m,
-                               int ncoarse) {
+                               int ncoarse, const int* __restrict__ frozen) {
+  if (frozen && *frozen) return;  // the instance has converged: its iterate stays as it is
   const int64_t tot = (int64_t)ncoarse * ndof;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = t / ndof + 1, i = t - (j - 1) * ndof;
@@ -2163,12 +2166,13 @@ hipError_t copy_launch(double* dst, const double* src, int64_t n, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t correct_launch(double* Vl, const double* Vc, int ndof, int m, int ncoarse, hipStream_t st) {
+hipError_t correct_launch(double* Vl, const double* Vc, int ndof, int m, int ncoarse, const int* frozen,
+                          hipStream_t st) {
   int64_t tot = (int64_t)ncoarse * ndof;
   if (tot <= 0) return hipSuccess;
   int64_t blocks = (tot + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(correct_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Vl, Vc, ndof, m, ncoarse);
+  hipLaunchKernelGGL(correct_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Vl, Vc, ndof, m, ncoarse, frozen);
   return hipGetLastError();
 }
 

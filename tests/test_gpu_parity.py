@@ -224,6 +224,34 @@ def test_graph_replay_matches_eager(torch, hetero):
         assert rel(first[i].cpu().numpy(), oracle_sequential(d)) <= EPS
 
 
+@pytest.mark.parametrize("graph", [0, 1])
+def test_batched_instances_stop_on_their_own(torch, graph):
+    """Each instance of a batch stops at its own MGRIT tolerance (Sec. 3's stopping criterion is
+    per problem): the faster instance keeps its iterate while the slower one iterates on, so the
+    batch returns what each instance's solve alone returns, with the same number of solves."""
+    fast = W.small("x", 3, 12, 64, kappa=0.05)["instances"][0]
+    slow = W.small("x", 3, 12, 64, kappa=1.0)["instances"][0]
+
+    def run(insts, tol=1e-6):
+        cfg = dict(instances=insts, m=4, max_levels=12, coarsest_max=4)
+        U, st = make_solver(cfg, tol=tol, use_graph=graph).solve_mgrit()
+        return [u.cpu().numpy() for u in U], st
+
+    say(f"case per-instance stop graph={graph}")
+    Ub, stb = run([fast, slow])
+    (Uf,), stf = run([fast])
+    (Us,), sts = run([slow])
+    (Uf9,), _ = run([fast], tol=1e-9)
+    gap = rel(Uf, Uf9)
+    say(f"  iters fast {stf['mgrit_iters']} slow {sts['mgrit_iters']} batch {stb['mgrit_iters']}; "
+        f"diff fast {rel(Ub[0], Uf):.1e} slow {rel(Ub[1], Us):.1e}; one more tolerance decade moves fast by {gap:.1e}")
+    assert stf["mgrit_iters"] < sts["mgrit_iters"] == stb["mgrit_iters"]
+    assert gap > 1e-9  # iterating the fast instance on would be seen below
+    assert rel(Ub[0], Uf) <= 1e-13 and rel(Ub[1], Us) <= 1e-13
+    assert stb["phi_calls"] == stf["phi_calls"] + sts["phi_calls"]
+    assert stb["vcycles"] == stf["vcycles"] + sts["vcycles"]
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_autotune_same_result(torch, precision):
     """The autotuner only moves work vectors between LDS and global scratch: same results."""
