@@ -157,6 +157,10 @@ struct pmgrit_handle {
   };
   std::vector<Group> groups;
   std::vector<int> launch_order;  // groups by decreasing cost: each sweep launches the costliest first
+  // >= 0: the MGRIT driver is issuing one group's work on that group's own stream (sweeps, fills and
+  // corrections cover only its instances); -1: every group, joined after each sweep
+  int only_group = -1;
+  std::vector<int> all_inst;  // 0 .. ninst - 1
   std::vector<int> inst_group;
   // learned warm start: the network and, per grid size, the samples of the single-step lists
   std::unique_ptr<NetState> net;
@@ -1369,6 +1373,16 @@ static hipError_t phi_timed(pmgrit_handle* H, const pmgrit_handle::Group& G, con
 template <class Pick>
 static hipError_t sweep(pmgrit_handle* H, Pick pick, int mode, hipStream_t st, int guess = -1, int kshift = 0) {
   hipError_t e;
+  if (H->only_group >= 0) {
+    pmgrit_handle::Group& G = H->groups[H->only_group];
+    const pmgrit_handle::JobList& J = pick(G);
+    if (J.n == 0) return hipSuccess;
+    PhiParams P = base_params(H, G, mode, J.d);
+    if (H->freeze_on) P.frozen = H->d_frozen;
+    if (guess >= 0) P.guess = guess;
+    P.kshift = kshift;
+    return phi_timed(H, G, P, J.n, st);
+  }
   int active = 0;
   for (pmgrit_handle::Group& G : H->groups) active += pick(G).n > 0;
   if (active == 0) return hipSuccess;
@@ -1395,10 +1409,18 @@ static hipError_t sweep(pmgrit_handle* H, Pick pick, int mode, hipStream_t st, i
 
 static int64_t sweep_steps(pmgrit_handle* H, int kind, int l) {
   int64_t s = 0;
-  for (pmgrit_handle::Group& G : H->groups)
+  for (int gi = 0; gi < (int)H->groups.size(); ++gi) {
+    if (H->only_group >= 0 && gi != H->only_group) continue;
+    pmgrit_handle::Group& G = H->groups[gi];
     s += kind == 0 ? G.jF[l].steps : kind == 1 ? G.jC[l].steps : kind == 2 ? G.jRES[l].steps
                                                                           : kind == 3 ? G.jCoarsest.steps : G.jSeq.steps;
+  }
   return s;
+}
+
+// the instances the driver is issuing work for (all, or those of the group of only_group)
+static const std::vector<int>& driven(pmgrit_handle* H) {
+  return H->only_group >= 0 ? H->groups[H->only_group].inst : H->all_inst;
 }
 
 // learned guesses written into the targets of a single-step list: which 0 sequential (shifted by
@@ -1434,12 +1456,12 @@ static hipError_t mgrit_cycle(pmgrit_handle* H, int l, int kind, hipStream_t st,
     return e;
   // F, C, F, residual (the interpolating F-relaxation is counted where it is launched)
   phi += 2 * sweep_steps(H, 0, l) + sweep_steps(H, 1, l) + sweep_steps(H, 2, l);
-  for (int i = 0; i < H->ninst; ++i) {
+  for (int i : driven(H)) {
     double* vc = H->h_vtab[(size_t)i * kMaxLevels + l + 1];
     if ((e = fill_launch(vc, (int64_t)(H->Nl[l + 1] + 1) * H->inst[i].ndof, 0.0, st)) != hipSuccess) return e;
   }
   if ((e = level_solve(H, l + 1, kind, st, phi)) != hipSuccess) return e;
-  for (int i = 0; i < H->ninst; ++i) {
+  for (int i : driven(H)) {
     double* vl = H->h_vtab[(size_t)i * kMaxLevels + l];
     double* vc = H->h_vtab[(size_t)i * kMaxLevels + l + 1];
     if ((e = correct_launch(vl, vc, H->inst[i].ndof, H->m, H->Nl[l + 1], H->freeze_on ? H->d_frozen + i : nullptr,
@@ -1663,6 +1685,7 @@ pmgrit_status pmgrit_create(int32_t n_instances, const pmgrit_problem* probs, co
   std::unique_ptr<pmgrit_handle> H(new pmgrit_handle());
   H->device = hip_device;
   H->ninst = n_instances;
+  for (int i = 0; i < n_instances; ++i) H->all_inst.push_back(i);
   H->mo = mo;
   H->so = so;
   H->Nt = probs[0].n_steps;
@@ -1861,10 +1884,13 @@ static hipError_t relax_level0(pmgrit_handle* h, hipStream_t st, bool learned, i
   if ((e = sweep(h, [](pmgrit_handle::Group& G) -> pmgrit_handle::JobList& { return G.jRES[0]; }, kModeResidual,
                  st)) != hipSuccess)
     return e;
-  for (pmgrit_handle::Group& G : h->groups)
+  for (int gi = 0; gi < (int)h->groups.size(); ++gi) {
+    if (h->only_group >= 0 && gi != h->only_group) continue;
+    pmgrit_handle::Group& G = h->groups[gi];
     if ((e = norm_reduce_launch(G.d_nrm2, G.d_res_begin, G.d_res_inst, h->d_resnorm, (int)G.inst.size(), st)) !=
         hipSuccess)
       return e;
+  }
   phi += 2 * sweep_steps(h, 0, 0) + sweep_steps(h, 1, 0) + sweep_steps(h, 2, 0);
   return hipSuccess;
 }
@@ -1873,17 +1899,44 @@ static hipError_t relax_level0(pmgrit_handle* h, hipStream_t st, bool learned, i
 // and add it to the level-0 C-points
 static hipError_t correct_level0(pmgrit_handle* h, hipStream_t st, double* const* u_out, int64_t& phi) {
   hipError_t e;
-  for (int i = 0; i < h->ninst; ++i) {
+  for (int i : driven(h)) {
     double* vc = h->h_vtab[(size_t)i * kMaxLevels + 1];
     if ((e = fill_launch(vc, (int64_t)(h->Nl[1] + 1) * h->inst[i].ndof, 0.0, st)) != hipSuccess) return e;
   }
   if ((e = level_solve(h, 1, h->mo.cycle, st, phi)) != hipSuccess) return e;
-  for (int i = 0; i < h->ninst; ++i) {
+  for (int i : driven(h)) {
     double* vc = h->h_vtab[(size_t)i * kMaxLevels + 1];
     if ((e = correct_launch(u_out[i], vc, h->inst[i].ndof, h->m, h->Nl[1], h->freeze_on ? h->d_frozen + i : nullptr,
                             st)) != hipSuccess)
       return e;
   }
+  return hipSuccess;
+}
+
+// one MGRIT iteration after the first: the coarse-grid correction, then the next level-0
+// relaxation. With several launch groups each group runs its whole iteration on its own stream
+// (groups share no vectors, scratch or job lists), so a group with short sweeps goes on to its
+// level-0 sweeps while a larger group is still in its narrow coarse-level sweeps, rather than all
+// groups meeting after every sweep.
+static hipError_t mgrit_iteration(pmgrit_handle* h, hipStream_t st, double* const* u_out, int64_t& phi) {
+  hipError_t e;
+  if (h->groups.size() == 1) {
+    if ((e = correct_level0(h, st, u_out, phi)) != hipSuccess) return e;
+    return relax_level0(h, st, false, phi);
+  }
+  if ((e = hipEventRecord(h->fork, st)) != hipSuccess) return e;
+  for (int gi : h->launch_order) {
+    pmgrit_handle::Group& G = h->groups[gi];
+    if ((e = hipStreamWaitEvent(G.stream, h->fork, 0)) != hipSuccess) return e;
+    h->only_group = gi;
+    e = correct_level0(h, G.stream, u_out, phi);
+    if (e == hipSuccess) e = relax_level0(h, G.stream, false, phi);
+    h->only_group = -1;
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(G.done, G.stream)) != hipSuccess) return e;
+  }
+  for (pmgrit_handle::Group& G : h->groups)
+    if ((e = hipStreamWaitEvent(st, G.done, 0)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -1903,8 +1956,7 @@ static pmgrit_status capture_iteration(pmgrit_handle* h, hipStream_t st, double*
   const int64_t nl0 = h->nlaunch_total, nw0 = h->nwg_total;
   hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipError_t eb = correct_level0(h, st, u_out, phi);
-    if (eb == hipSuccess) eb = relax_level0(h, st, false, phi);
+    hipError_t eb = mgrit_iteration(h, st, u_out, phi);
     e = hipStreamEndCapture(st, &g);
     if (eb != hipSuccess) e = eb;
   }
@@ -2034,8 +2086,7 @@ pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* con
         HIPCHK(graph_launch_timed(h, st));
         it_phi = h->graph_phi;
       } else {
-        HIPCHK(correct_level0(h, st, u_out_dev, it_phi));
-        HIPCHK(relax_level0(h, st, false, it_phi));
+        HIPCHK(mgrit_iteration(h, st, u_out_dev, it_phi));
       }
       int active = 0;
       for (int i = 0; i < h->ninst; ++i) active += h->h_frozen[i] ? 0 : 1;
