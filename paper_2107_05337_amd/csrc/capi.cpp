@@ -142,6 +142,7 @@ struct pmgrit_handle {
     // interval, and one step per instance (sequential stepping, shifted by k)
     std::vector<JobList> jF1;
     JobList jC1;  // the level-0 C-steps of the learned first iteration (flags: which are predicted)
+    bool netfree = false;  // no instance of the group is predicted by the network in MGRIT
     JobList jSeq1;
     int max_jobs = 0;
     double* d_ws = nullptr;
@@ -160,6 +161,7 @@ struct pmgrit_handle {
   // >= 0: the MGRIT driver is issuing one group's work on that group's own stream (sweeps, fills and
   // corrections cover only its instances); -1: every group, joined after each sweep
   int only_group = -1;
+  bool skip_netfree = false;  // sweeps leave out the groups marked netfree
   std::vector<int> all_inst;  // 0 .. ninst - 1
   std::vector<int> inst_group;
   // learned warm start: the network and, per grid size, the samples of the single-step lists
@@ -955,6 +957,7 @@ static pmgrit_status learned_setup(pmgrit_handle* H) {
     for (int j = 1; j * m <= N0; ++j) emit(i, j * m - 1);
   };
   for (pmgrit_handle::Group& G : H->groups) {
+    G.netfree = std::none_of(G.inst.begin(), G.inst.end(), net_on);
     G.jF1.resize(std::max(m - 1, 1));
     for (int s = 0; s + 1 < m; ++s) {
       std::vector<PhiJob> J;
@@ -1368,6 +1371,12 @@ static hipError_t phi_timed(pmgrit_handle* H, const pmgrit_handle::Group& G, con
   return hipEventRecord(H->ev[2 * k + 1], st);
 }
 
+// whether the driver is issuing work for launch group gi
+static bool drives(const pmgrit_handle* H, int gi) {
+  if (H->only_group >= 0) return gi == H->only_group;
+  return !(H->skip_netfree && H->groups[gi].netfree);
+}
+
 // one sweep: the given job list of every group, groups concurrently on their own streams
 // (fork and join through events on the caller's stream)
 template <class Pick>
@@ -1384,14 +1393,14 @@ static hipError_t sweep(pmgrit_handle* H, Pick pick, int mode, hipStream_t st, i
     return phi_timed(H, G, P, J.n, st);
   }
   int active = 0;
-  for (pmgrit_handle::Group& G : H->groups) active += pick(G).n > 0;
+  for (int gi = 0; gi < (int)H->groups.size(); ++gi) active += drives(H, gi) && pick(H->groups[gi]).n > 0;
   if (active == 0) return hipSuccess;
   const bool fork = active > 1;
   if (fork && (e = hipEventRecord(H->fork, st)) != hipSuccess) return e;
   for (int gi : H->launch_order) {
     pmgrit_handle::Group& G = H->groups[gi];
     const pmgrit_handle::JobList& J = pick(G);
-    if (J.n == 0) continue;
+    if (J.n == 0 || !drives(H, gi)) continue;
     hipStream_t gs = fork ? G.stream : st;
     if (fork && (e = hipStreamWaitEvent(gs, H->fork, 0)) != hipSuccess) return e;
     PhiParams P = base_params(H, G, mode, J.d);
@@ -1402,15 +1411,17 @@ static hipError_t sweep(pmgrit_handle* H, Pick pick, int mode, hipStream_t st, i
     if (fork && (e = hipEventRecord(G.done, gs)) != hipSuccess) return e;
   }
   if (fork)
-    for (pmgrit_handle::Group& G : H->groups)
-      if (pick(G).n > 0 && (e = hipStreamWaitEvent(st, G.done, 0)) != hipSuccess) return e;
+    for (int gi = 0; gi < (int)H->groups.size(); ++gi)
+      if (drives(H, gi) && pick(H->groups[gi]).n > 0 &&
+          (e = hipStreamWaitEvent(st, H->groups[gi].done, 0)) != hipSuccess)
+        return e;
   return hipSuccess;
 }
 
 static int64_t sweep_steps(pmgrit_handle* H, int kind, int l) {
   int64_t s = 0;
   for (int gi = 0; gi < (int)H->groups.size(); ++gi) {
-    if (H->only_group >= 0 && gi != H->only_group) continue;
+    if (!drives(H, gi)) continue;
     pmgrit_handle::Group& G = H->groups[gi];
     s += kind == 0 ? G.jF[l].steps : kind == 1 ? G.jC[l].steps : kind == 2 ? G.jRES[l].steps
                                                                           : kind == 3 ? G.jCoarsest.steps : G.jSeq.steps;
@@ -1885,7 +1896,7 @@ static hipError_t relax_level0(pmgrit_handle* h, hipStream_t st, bool learned, i
                  st)) != hipSuccess)
     return e;
   for (int gi = 0; gi < (int)h->groups.size(); ++gi) {
-    if (h->only_group >= 0 && gi != h->only_group) continue;
+    if (!drives(h, gi)) continue;
     pmgrit_handle::Group& G = h->groups[gi];
     if ((e = norm_reduce_launch(G.d_nrm2, G.d_res_begin, G.d_res_inst, h->d_resnorm, (int)G.inst.size(), st)) !=
         hipSuccess)
@@ -1937,6 +1948,39 @@ static hipError_t mgrit_iteration(pmgrit_handle* h, hipStream_t st, double* cons
   }
   for (pmgrit_handle::Group& G : h->groups)
     if ((e = hipStreamWaitEvent(st, G.done, 0)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+// The first level-0 relaxation. Without the learned guess every group relaxes whole on its own
+// stream, as in the later iterations. With it, the groups holding an instance the network predicts
+// go step position by position, joined at every sweep (one position's predictions span those
+// groups), while every other group relaxes whole on its own stream meanwhile.
+static hipError_t relax_first(pmgrit_handle* h, hipStream_t st, bool learned, int64_t& phi) {
+  if (h->groups.size() == 1) return relax_level0(h, st, learned, phi);
+  hipError_t e;
+  if ((e = hipEventRecord(h->fork, st)) != hipSuccess) return e;
+  bool any_net = false;
+  for (int gi : h->launch_order) {
+    pmgrit_handle::Group& G = h->groups[gi];
+    if (learned && !G.netfree) {
+      any_net = true;
+      continue;
+    }
+    if ((e = hipStreamWaitEvent(G.stream, h->fork, 0)) != hipSuccess) return e;
+    h->only_group = gi;
+    e = relax_level0(h, G.stream, false, phi);
+    h->only_group = -1;
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(G.done, G.stream)) != hipSuccess) return e;
+  }
+  if (any_net) {
+    h->skip_netfree = true;
+    e = relax_level0(h, st, true, phi);
+    h->skip_netfree = false;
+    if (e != hipSuccess) return e;
+  }
+  for (pmgrit_handle::Group& G : h->groups)
+    if ((!learned || G.netfree) && (e = hipStreamWaitEvent(st, G.done, 0)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -2036,7 +2080,7 @@ pmgrit_status pmgrit_solve_mgrit(pmgrit_handle* h, void* hip_stream, double* con
     std::vector<double> r0(h->ninst, -1.0), rfix(h->ninst, 0.0);
     std::memset(h->h_frozen, 0, sizeof(int) * h->ninst);
     HIPCHK(hipMemcpyAsync(h->d_frozen, h->h_frozen, sizeof(int) * h->ninst, hipMemcpyHostToDevice, st));
-    HIPCHK(relax_level0(h, st, h->so.guess == 3, phi));
+    HIPCHK(relax_first(h, st, h->so.guess == 3, phi));
     for (;;) {
       HIPCHK(hipMemcpyAsync(h->h_pinned, h->d_resnorm, sizeof(double) * h->ninst, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
