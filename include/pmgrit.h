@@ -317,8 +317,9 @@ pmgrit_status pmgrit_info(const pmgrit_handle* h, int64_t* out8);
 
 /* Launch group of an instance.  Instances are grouped by the LDS placement their sizes allow;
  * each group launches with its own configuration on its own stream, forked from and joined
- * back into the caller's stream at every sweep of the first MGRIT relaxation and of sequential
- * stepping, and once per MGRIT iteration after that.  out8 = {group id, number of groups, LDS mask
+ * back into the caller's stream at every sweep of sequential stepping, and once per MGRIT
+ * iteration (with the learned guess, the groups holding a predicted instance also meet at every
+ * sweep of the first relaxation).  out8 = {group id, number of groups, LDS mask
  * of the sweeps with at most as many workgroups as the device has CUs | LDS mask of the wider
  * sweeps << 8 (masks as in pmgrit_solver_opts.lds_mask), dynamic LDS bytes of the first,
  * off-block entries per lane of the triangular solves, instances in the group, largest dof
