@@ -224,6 +224,28 @@ def test_graph_replay_matches_eager(torch, hetero):
         assert rel(first[i].cpu().numpy(), oracle_sequential(d)) <= EPS
 
 
+def test_learned_mgrit_two_launch_groups(torch):
+    """MGRIT with the learned guess over two launch groups, one of which holds no instance the network
+    predicts (more than 64 elements per direction): that group relaxes whole on its own stream while
+    the other goes step position by position. Both reach the oracle's trajectory, and the instance
+    the network does not predict is bitwise the one of a solve without the network."""
+    insts = [dict(p=2, n=8, domain=0, kappa=1.0, T=0.1, Nt=128, src=W.random_modes(21, 3, 4), tkind=0, init=[]),
+             dict(p=4, n=128, domain=1, kappa=0.5, T=0.1, Nt=128, src=W.random_modes(22, 3, 4), tkind=0, init=[])]
+    cfg = dict(instances=insts, m=4, max_levels=4, coarsest_max=4)
+    say("case learned MGRIT over two launch groups")
+    S = make_solver(cfg, guess=3, tol=1e-12)
+    assert S.group_info(0)["groups"] == 2
+    S.net_load(W.net_init(3))
+    U, st = S.solve_mgrit()
+    S2 = make_solver(cfg, guess=2, tol=1e-12)
+    U2, st2 = S2.solve_mgrit()
+    say(f"  iters learned {st['mgrit_iters']} previous-iterate {st2['mgrit_iters']}; "
+        f"V-cycles {st['vcycles']} / {st2['vcycles']}")
+    assert torch.equal(U[1], U2[1])
+    for i, d in enumerate(insts):
+        assert rel(U[i].cpu().numpy(), oracle_sequential(d)) <= EPS
+
+
 @pytest.mark.parametrize("graph", [0, 1])
 def test_batched_instances_stop_on_their_own(torch, graph):
     """Each instance of a batch stops at its own MGRIT tolerance (Sec. 3's stopping criterion is
