@@ -1429,7 +1429,8 @@ static int64_t sweep_steps(pmgrit_handle* H, int kind, int l) {
   return s;
 }
 
-// the instances the driver is issuing work for (all, or those of the group of only_group)
+// the instances the driver is issuing fills and corrections for (all, or those of the group of
+// only_group; skip_netfree is set only around the first relaxation, which has neither)
 static const std::vector<int>& driven(pmgrit_handle* H) {
   return H->only_group >= 0 ? H->groups[H->only_group].inst : H->all_inst;
 }
